@@ -1,0 +1,166 @@
+/*
+ * sketch.h -- C ABI of libsketch.so, an MI355X (gfx950) library that applies
+ * sparse oblivious subspace embeddings to tall matrices.
+ *
+ * Method: "Randomized Sketching is Robust to Low-Precision Rounding on GPUs"
+ * (Jeendgar, Flint, Anzt).  Given A (m x n, m >> n) and a random S (d x m),
+ * form SA (Section 1; Section 2.1).  S is a SparseStack matrix: s stacked
+ * CountSketch blocks of d/s rows, one nonzero +-1/sqrt(s) per block and
+ * column (Section 2.2, SparseStack definition; block ranges and the value
+ * scale in Section 4.1); s = 1 is CountSketch (Section 2.2).  SA is
+ * accumulated in FP32, or in FP16 with one of three rounding rules:
+ * round-to-nearest, exact stochastic rounding, dithered rounding (Section
+ * 2.3; Section 4.2).
+ *
+ * Conventions
+ *  - Every function returns SK_OK (0) or a negative SK_E* code; the message
+ *    of the last failure on the calling thread is in sketch_last_error().
+ *  - Matrices are row-major with an explicit leading dimension in elements.
+ *  - Pointers named A, SA, x, out, buckets, signs are DEVICE pointers owned by
+ *    the caller; the library never frees or keeps them past the call.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously; HIP errors of a launch are returned when detected at
+ *    launch time, later asynchronous faults surface on a later call.
+ *  - Argument checks run before any HIP call, so invalid calls fail the same
+ *    way on a machine without a GPU.
+ *  - A handle may be used by one thread at a time; distinct handles are
+ *    independent.
+ */
+#ifndef SKETCH_H
+#define SKETCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define SK_OK            0
+#define SK_EINVAL       -1   /* bad argument (shape, pointer, flag, code)     */
+#define SK_EUNSUPPORTED -2   /* valid but not supported (alignment, size)     */
+#define SK_ENOMEM       -3   /* device allocation failed                      */
+#define SK_EHIP         -4   /* a HIP runtime call failed                     */
+
+/* ---- element types ----------------------------------------------------- */
+#define SK_F32  0
+#define SK_F16  1
+#define SK_BF16 2
+
+/* ---- accumulation of SA (fixed per handle) ----------------------------- */
+#define SK_ACC_F32        0  /* SA is FP32                                    */
+#define SK_ACC_F16_RN     1  /* SA is FP16, round-to-nearest-even            */
+#define SK_ACC_F16_SR     2  /* SA is FP16, exact stochastic rounding        */
+#define SK_ACC_F16_DITHER 3  /* SA is FP16, dithered rounding                */
+
+/* ---- sketch_apply flags ------------------------------------------------ */
+#define SK_ACCUMULATE 1u     /* SA += S*A instead of SA = S*A                 */
+
+typedef struct sk_sketch *sk_handle;
+
+/*
+ * Work decomposition of one sketch_apply call.  Rows are cut into units of
+ * `chunk_rows` consecutive rows; each unit is summed in FP32 by one workgroup
+ * per column tile (and per group of `block_group` SparseStack blocks) and
+ * then added into SA once.  In the FP16 modes each unit's partial is scaled
+ * by fl32(1/sqrt(s)), rounded to FP16 with the handle's rule, and added with
+ * FP16 round-to-nearest atomics, so `chunk_rows` fixes the rounding sites:
+ * site q of entry (b, c) in the unit starting at global row r0 is
+ * q = r0*d*n + b*n + c.  Zero fields mean "choose automatically".
+ */
+typedef struct sk_schedule {
+    int32_t chunk_rows;   /* rows per unit, a multiple of 64                  */
+    int32_t block_group;  /* blocks per workgroup: 1, 2, 4 or 8, dividing s   */
+    int32_t waves;        /* waves (64 lanes) per workgroup: 4, 8 or 16       */
+    int32_t xcd_remap;    /* 1: place all tiles of a unit on one XCD; 0: off  */
+    int32_t reserved[4];  /* must be zero                                     */
+} sk_schedule;
+
+/*
+ * sketch_create -- describe S (d x m) once.
+ *   m        >= 1, number of columns of S (rows of the full A).
+ *   d        >= 1, sketch rows; d % s == 0 (Section 4.1 assumes it).
+ *   s        1..16, nonzeros per column (the paper's zeta).
+ *   seed     64-bit key of the row hash; S is a pure function of (m, d, s,
+ *            seed) and hash version 1, never stored.
+ *   rounding SK_ACC_F32 / SK_ACC_F16_RN / SK_ACC_F16_SR / SK_ACC_F16_DITHER.
+ *   out      receives the handle.
+ * Allocates no device memory.  Errors: SK_EINVAL.
+ */
+int sketch_create(int64_t m, int64_t d, int32_t s, uint64_t seed, int32_t rounding,
+                  sk_handle *out);
+
+/* sketch_destroy -- free the handle and its workspace (NULL is accepted). */
+int sketch_destroy(sk_handle h);
+
+/*
+ * sketch_apply -- SA = S[:, row_offset : row_offset+rows] * A  (Section 4.1,
+ * SparseStack accumulation; Section 4.2 for the FP16 modes).
+ *   A          device, rows x n, element type a_dtype (SK_F32/F16/BF16),
+ *              leading dimension lda >= n.  May be NULL when rows == 0.
+ *   row_offset first global row; row_offset + rows <= m.  The hash uses
+ *              global row indices, so calls on consecutive row ranges with
+ *              SK_ACCUMULATE reproduce one call on the whole range.
+ *   SA         device, d x n, FP32 for SK_ACC_F32 else FP16 (raw 16-bit),
+ *              leading dimension ldsa >= n.  FP16 SA must be 4-byte aligned
+ *              with ldsa even (packed FP16 atomics).
+ *   flags      0 or SK_ACCUMULATE.
+ *   round_epoch selects the rounding-noise stream of the SR / dither modes
+ *              (S does not change with it).
+ * FP32 mode: SA = fl32(fl32(1/sqrt(s)) * sum) with the sum accumulated in
+ * FP32 in an unspecified order (exact for integer-valued A whose partial sums
+ * stay below 2^24).  FP16 modes: see sk_schedule.
+ * The call enqueues work on `stream` and returns; it does not synchronise.
+ * Errors: SK_EINVAL (shapes, pointers, flags), SK_EUNSUPPORTED (alignment,
+ * d too large for any schedule), SK_ENOMEM, SK_EHIP.
+ */
+int sketch_apply(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int64_t n,
+                 int64_t lda, int64_t row_offset, void *SA, int64_t ldsa, uint32_t flags,
+                 uint32_t round_epoch, void *stream);
+
+/*
+ * sketch_set_schedule -- force a schedule for later sketch_apply calls on h
+ * (NULL restores the automatic choice).  Fields are checked against the
+ * handle at apply time.  Errors: SK_EINVAL (bad field values).
+ */
+int sketch_set_schedule(sk_handle h, const sk_schedule *sched);
+
+/*
+ * sketch_plan -- the schedule sketch_apply would use for (a_dtype, rows, n)
+ * on this handle and the current device, written to *out.  Errors:
+ * SK_EINVAL, SK_EUNSUPPORTED, SK_EHIP (device query).
+ */
+int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedule *out);
+
+/*
+ * sketch_hash -- the S entries of global rows row_begin .. row_begin+count-1
+ * (Section 2.2 SparseStack definition, hash version 1): buckets[i*s + j] in
+ * [j*d/s, (j+1)*d/s) and signs[i*s + j] in {-1, +1}.  Device int32 / int8
+ * arrays of count*s entries.  A debugging and testing export.
+ * Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t *buckets,
+                int8_t *signs, void *stream);
+
+/*
+ * sketch_quantize -- the FP16 rounding rules of Section 4.2 applied to
+ * `count` FP32 values: out[k] = Q_mode(x[k]) with rounding noise of site
+ * site0 + k under (seed, epoch).  mode: SK_ACC_F16_RN / _SR / _DITHER.  x and
+ * out are device arrays (out receives FP16 bit patterns).  A testing export
+ * of exactly the quantiser the FP16 modes of sketch_apply use.
+ * Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_quantize(int32_t mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
+                    uint32_t epoch, uint64_t site0, void *stream);
+
+/* sketch_last_error -- message of the last failure on this thread ("" if none). */
+const char *sketch_last_error(void);
+
+/* sketch_version -- library version * 100 + hash version. */
+int sketch_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKETCH_H */

@@ -1,0 +1,134 @@
+"""Sparse oblivious subspace embeddings on MI355X (gfx950).
+
+Python binding of libsketch.so (include/sketch.h).  PyTorch supplies device
+memory and streams; the binding only marshals tensor pointers, shapes and
+the current HIP stream into the C ABI.  All arithmetic happens in the
+library's HIP kernels.
+
+    sk = Sketch(m, d, s, seed, rounding=ACC_F16_RN)
+    SA = sk.apply(A)                      # A: (rows, n) CUDA tensor
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, F16, F32,
+                   Schedule, SketchError, check, load)
+
+__all__ = ["Sketch", "SketchError", "Schedule", "quantize", "version", "ACC_F32", "ACC_F16_RN",
+           "ACC_F16_SR", "ACC_F16_DITHER", "F32", "F16", "BF16", "ACCUMULATE"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float16:
+        return F16
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _matrix(t, name):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be a 2-D tensor with unit column stride" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    return t.stride(0)
+
+
+def version():
+    return load().sketch_version()
+
+
+class Sketch:
+    """S (d x m) = SparseStack with s nonzeros per column (s = 1: CountSketch)."""
+
+    def __init__(self, m, d, s, seed=0, rounding=ACC_F32):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        check(self._lib.sketch_create(int(m), int(d), int(s), int(seed) & (2 ** 64 - 1), int(rounding),
+                                      ctypes.byref(h)), "sketch_create")
+        self._h = h
+        self.m, self.d, self.s, self.seed, self.rounding = int(m), int(d), int(s), int(seed), int(rounding)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sketch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def out_dtype(self):
+        torch = _torch()
+        return torch.float32 if self.rounding == ACC_F32 else torch.float16
+
+    def empty_output(self, n, device=None):
+        torch = _torch()
+        return torch.empty((self.d, n), dtype=self.out_dtype, device=device or "cuda")
+
+    def apply(self, A, SA=None, row_offset=0, accumulate=False, epoch=0, stream=None):
+        """SA = S[:, row_offset:row_offset+rows] @ A (or +=, with accumulate)."""
+        lda = _matrix(A, "A")
+        rows, n = A.shape
+        if SA is None:
+            SA = self.empty_output(n, A.device)
+        ldsa = _matrix(SA, "SA")
+        if SA.dtype != self.out_dtype or tuple(SA.shape) != (self.d, n):
+            raise ValueError("SA must be a (%d, %d) %s tensor" % (self.d, n, self.out_dtype))
+        check(self._lib.sketch_apply(self._h, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), rows, n, lda,
+                                     int(row_offset), ctypes.c_void_p(SA.data_ptr()), ldsa,
+                                     ACCUMULATE if accumulate else 0, int(epoch) & 0xFFFFFFFF,
+                                     _stream(stream)), "sketch_apply")
+        return SA
+
+    def set_schedule(self, chunk_rows=0, block_group=0, waves=0, xcd_remap=1):
+        sch = Schedule(chunk_rows, block_group, waves, xcd_remap)
+        check(self._lib.sketch_set_schedule(self._h, ctypes.byref(sch)), "sketch_set_schedule")
+
+    def clear_schedule(self):
+        check(self._lib.sketch_set_schedule(self._h, None), "sketch_set_schedule")
+
+    def plan(self, a_dtype, rows, n):
+        sch = Schedule()
+        check(self._lib.sketch_plan(self._h, int(a_dtype), int(rows), int(n), ctypes.byref(sch)), "sketch_plan")
+        return sch.as_dict()
+
+    def hash(self, row_begin, count, stream=None):
+        """Device (buckets int32 [count, s], signs int8 [count, s])."""
+        torch = _torch()
+        b = torch.empty((count, self.s), dtype=torch.int32, device="cuda")
+        g = torch.empty((count, self.s), dtype=torch.int8, device="cuda")
+        check(self._lib.sketch_hash(self._h, int(row_begin), int(count), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(g.data_ptr()), _stream(stream)), "sketch_hash")
+        return b, g
+
+
+def quantize(mode, x, seed=0, epoch=0, site0=0, stream=None):
+    """FP16 bit patterns (int16 tensor) of x (FP32 device tensor) under rule `mode`."""
+    torch = _torch()
+    if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x must be a contiguous FP32 device tensor")
+    out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    check(load().sketch_quantize(int(mode), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 x.numel(), int(seed) & (2 ** 64 - 1), int(epoch) & 0xFFFFFFFF, int(site0),
+                                 _stream(stream)), "sketch_quantize")
+    return out

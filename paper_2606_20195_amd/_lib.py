@@ -1,0 +1,77 @@
+"""ctypes loading of libsketch.so and the raw C-ABI signatures.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libsketch.so.  Importing this module fails loudly when the library
+has not been built (``python -m paper_2606_20195_amd.build``); there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsketch.so")
+
+# return codes (include/sketch.h)
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+F32, F16, BF16 = 0, 1, 2
+ACC_F32, ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER = 0, 1, 2, 3
+ACCUMULATE = 1
+
+EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedule", "sketch_plan",
+           "sketch_hash", "sketch_quantize", "sketch_last_error", "sketch_version")
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("chunk_rows", ctypes.c_int32), ("block_group", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+    def as_dict(self):
+        return dict(chunk_rows=self.chunk_rows, block_group=self.block_group, waves=self.waves,
+                    xcd_remap=self.xcd_remap)
+
+
+class SketchError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsketch.so is not built; run python -m paper_2606_20195_amd.build "
+                          "(expected at %s)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "sketch_create": ([i64, i64, i32, u64, i32, ctypes.POINTER(P)], ctypes.c_int),
+        "sketch_destroy": ([P], ctypes.c_int),
+        "sketch_apply": ([P, P, i32, i64, i64, i64, i64, P, i64, u32, u32, P], ctypes.c_int),
+        "sketch_set_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "sketch_plan": ([P, i32, i64, i64, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "sketch_hash": ([P, i64, i64, P, P, P], ctypes.c_int),
+        "sketch_quantize": ([i32, P, P, i64, u64, u32, u64, P], ctypes.c_int),
+        "sketch_last_error": ([], ctypes.c_char_p),
+        "sketch_version": ([], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(rc, where):
+    if rc != OK:
+        msg = load().sketch_last_error().decode(errors="replace")
+        raise SketchError(rc, where, msg)
+    return rc

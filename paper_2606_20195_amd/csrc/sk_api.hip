@@ -1,0 +1,338 @@
+// C ABI of libsketch.so: argument checks, planning and launches.
+// The argument checks run before any HIP call so that invalid calls fail the
+// same way with or without a GPU.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "sk_internal.hpp"
+
+#define SK_LIB_VERSION 1
+#define SK_HASH_VERSION 1
+
+namespace sk {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* what)
+{
+    return set_error(SK_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int device_info(DeviceInfo* out)
+{
+    static std::mutex mu;
+    static DeviceInfo cache[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return set_error(SK_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache[dev].device != dev) {
+        int cus = 0, lds = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CU count)");
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(LDS size)");
+        cache[dev].device = dev;
+        cache[dev].cus = cus > 0 ? cus : 1;
+        cache[dev].lds_max = (size_t)lds;
+    }
+    *out = cache[dev];
+    return SK_OK;
+}
+
+static int elem_size(int32_t dt)
+{
+    return dt == SK_F32 ? 4 : (dt == SK_F16 || dt == SK_BF16) ? 2 : 0;
+}
+
+int apply_max_waves(int32_t a_dtype);
+
+int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo& dev,
+              Plan* out)
+{
+    const int64_t W = h->d / h->s;
+    const sk_schedule* f = h->forced ? &h->sched : nullptr;
+    Plan pl;
+    // blocks per workgroup
+    if (f && f->block_group) {
+        pl.bg = f->block_group;
+        if (h->s % pl.bg) return set_error(SK_EINVAL, "block_group %d does not divide s = %d", pl.bg, h->s);
+        if (apply_lds_bytes(pl.bg, W) > dev.lds_max)
+            return set_error(SK_EUNSUPPORTED, "block_group %d needs %zu B of LDS (device has %zu)", pl.bg,
+                             apply_lds_bytes(pl.bg, W), dev.lds_max);
+    } else {
+        for (int bg : {8, 4, 2, 1}) {
+            if (h->s % bg == 0 && apply_lds_bytes(bg, W) <= dev.lds_max) {
+                pl.bg = bg;
+                break;
+            }
+        }
+        if (!pl.bg)
+            return set_error(SK_EUNSUPPORTED, "d/s = %lld bucket rows of 32 FP32 values exceed the %zu B of LDS",
+                             (long long)W, dev.lds_max);
+    }
+    pl.lds_bytes = apply_lds_bytes(pl.bg, W);
+    pl.bgroups = h->s / pl.bg;
+    pl.col_tiles = (int32_t)((n + 31) / 32);
+    const int maxw = apply_max_waves(a_dtype);
+    pl.waves = (f && f->waves) ? f->waves : maxw;
+    if (pl.waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", pl.waves, maxw);
+    const int64_t per_unit = (int64_t)pl.col_tiles * pl.bgroups;
+    const int esz = elem_size(a_dtype);
+    // A unit is addressed through one buffer resource: keep it below 2 GiB.
+    const int64_t max_chunk = ((((int64_t)1 << 31) - 1) / (lda * esz)) / 64 * 64;
+    if (max_chunk < 64) return set_error(SK_EUNSUPPORTED, "64 rows of lda = %lld exceed 2 GiB", (long long)lda);
+    if (f && f->chunk_rows) {
+        pl.chunk_rows = f->chunk_rows;
+        if (pl.chunk_rows > max_chunk)
+            return set_error(SK_EUNSUPPORTED, "chunk_rows = %d spans more than 2 GiB", pl.chunk_rows);
+    } else {
+        const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)(dev.lds_max / pl.lds_bytes));
+        const int64_t target = std::max<int64_t>(1, (int64_t)dev.cus * wg_per_cu / per_unit);
+        int64_t chunk = (rows + target - 1) / target;
+        chunk = (chunk + 63) / 64 * 64;
+        chunk = std::max<int64_t>(chunk, 2048);
+        chunk = std::min<int64_t>(chunk, max_chunk);
+        pl.chunk_rows = (int32_t)chunk;
+    }
+    pl.units = rows > 0 ? (rows + pl.chunk_rows - 1) / pl.chunk_rows : 0;
+    if (pl.units * per_unit > 0x7FFFFFFF) return set_error(SK_EUNSUPPORTED, "grid too large");
+    const int want_remap = f ? f->xcd_remap : 1;
+    pl.xcd_remap = (want_remap && per_unit > 1 && pl.units % 8 == 0) ? 1 : 0;
+    *out = pl;
+    return SK_OK;
+}
+
+static int check_schedule(const sk_schedule* s)
+{
+    if (s->chunk_rows < 0 || s->chunk_rows % 64)
+        return set_error(SK_EINVAL, "chunk_rows must be a non-negative multiple of 64");
+    if (s->block_group && s->block_group != 1 && s->block_group != 2 && s->block_group != 4 && s->block_group != 8)
+        return set_error(SK_EINVAL, "block_group must be 0, 1, 2, 4 or 8");
+    if (s->waves && s->waves != 4 && s->waves != 8 && s->waves != 16)
+        return set_error(SK_EINVAL, "waves must be 0, 4, 8 or 16");
+    if (s->xcd_remap != 0 && s->xcd_remap != 1) return set_error(SK_EINVAL, "xcd_remap must be 0 or 1");
+    for (int i = 0; i < 4; ++i)
+        if (s->reserved[i]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
+    return SK_OK;
+}
+
+static float value_scale32(int32_t s) { return (float)(1.0 / std::sqrt((double)s)); }
+static bool scale_is_pow2(int32_t s) { return s == 1 || s == 4 || s == 16; }
+
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+int sketch_version(void) { return SK_LIB_VERSION * 100 + SK_HASH_VERSION; }
+
+const char* sketch_last_error(void) { return g_err; }
+
+int sketch_create(int64_t m, int64_t d, int32_t s, uint64_t seed, int32_t rounding, sk_handle* out)
+{
+    if (!out) return set_error(SK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (m < 1) return set_error(SK_EINVAL, "m = %lld must be >= 1", (long long)m);
+    if (s < 1 || s > 16) return set_error(SK_EINVAL, "s = %d must be in 1..16", s);
+    if (d < 1 || d % s) return set_error(SK_EINVAL, "d = %lld must be >= 1 and a multiple of s = %d", (long long)d, s);
+    if (d / s > (1LL << 24)) return set_error(SK_EUNSUPPORTED, "d/s = %lld too large", (long long)(d / s));
+    if (rounding < SK_ACC_F32 || rounding > SK_ACC_F16_DITHER)
+        return set_error(SK_EINVAL, "unknown rounding code %d", rounding);
+    sk_sketch* h = new (std::nothrow) sk_sketch;
+    if (!h) return set_error(SK_ENOMEM, "out of host memory");
+    h->m = m;
+    h->d = d;
+    h->s = s;
+    h->seed = seed;
+    h->rounding = rounding;
+    *out = h;
+    return SK_OK;
+}
+
+int sketch_destroy(sk_handle h)
+{
+    if (!h) return SK_OK;
+    if (h->ws) (void)hipFree(h->ws);
+    delete h;
+    return SK_OK;
+}
+
+int sketch_set_schedule(sk_handle h, const sk_schedule* sched)
+{
+    if (!h) return set_error(SK_EINVAL, "handle is NULL");
+    if (!sched) {
+        h->forced = false;
+        return SK_OK;
+    }
+    int rc = check_schedule(sched);
+    if (rc) return rc;
+    h->sched = *sched;
+    h->forced = true;
+    return SK_OK;
+}
+
+int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedule* out)
+{
+    if (!h || !out) return set_error(SK_EINVAL, "NULL argument");
+    if (!elem_size(a_dtype)) return set_error(SK_EINVAL, "unknown element type %d", a_dtype);
+    if (rows < 0 || n < 1) return set_error(SK_EINVAL, "bad shape");
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+    Plan pl;
+    rc = make_plan(h, a_dtype, rows, n, n, dev, &pl);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->chunk_rows = pl.chunk_rows;
+    out->block_group = pl.bg;
+    out->waves = pl.waves;
+    out->xcd_remap = pl.xcd_remap;
+    return SK_OK;
+}
+
+int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
+                 int64_t row_offset, void* SA, int64_t ldsa, uint32_t flags, uint32_t round_epoch, void* stream)
+{
+    if (!h) return set_error(SK_EINVAL, "handle is NULL");
+    const int esz = elem_size(a_dtype);
+    if (!esz) return set_error(SK_EINVAL, "unknown element type %d", a_dtype);
+    if (rows < 0 || n < 1 || n > (1LL << 30)) return set_error(SK_EINVAL, "bad shape rows=%lld n=%lld",
+                                                               (long long)rows, (long long)n);
+    if (lda < n) return set_error(SK_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
+    if (row_offset < 0 || row_offset + rows > h->m)
+        return set_error(SK_EINVAL, "rows [%lld, %lld) outside the sketch's m = %lld", (long long)row_offset,
+                         (long long)(row_offset + rows), (long long)h->m);
+    if (!SA) return set_error(SK_EINVAL, "SA is NULL");
+    if (ldsa < n) return set_error(SK_EINVAL, "ldsa = %lld < n = %lld", (long long)ldsa, (long long)n);
+    if (rows > 0 && !A) return set_error(SK_EINVAL, "A is NULL");
+    if (flags & ~SK_ACCUMULATE) return set_error(SK_EINVAL, "unknown flags 0x%x", flags);
+    const bool f16 = h->rounding != SK_ACC_F32;
+    if (f16 && (((uintptr_t)SA & 3u) || (ldsa & 1)))
+        return set_error(SK_EUNSUPPORTED, "FP16 SA needs a 4-byte aligned base and an even ldsa");
+    if (!f16 && ((uintptr_t)SA & 3u)) return set_error(SK_EINVAL, "FP32 SA is not 4-byte aligned");
+    if (rows > 0 && ((uintptr_t)A % (uintptr_t)esz)) return set_error(SK_EINVAL, "A is not element aligned");
+    const bool accumulate = (flags & SK_ACCUMULATE) != 0;
+
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+    Plan pl;
+    if (rows > 0) {
+        rc = make_plan(h, a_dtype, rows, n, lda, dev, &pl);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+
+    ApplyArgs a{};
+    a.A = A;
+    a.lda = lda;
+    a.rows = rows;
+    a.row_offset = row_offset;
+    a.n = (int32_t)n;
+    a.d = (int32_t)h->d;
+    a.s = h->s;
+    a.W = (uint32_t)(h->d / h->s);
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    a.chunk_rows = pl.chunk_rows;
+    a.col_tiles = pl.col_tiles;
+    a.bgroups = pl.bgroups;
+    a.epoch = round_epoch;
+    a.xcd_remap = pl.xcd_remap;
+    const uintptr_t vec_align = esz == 4 ? 8u : 4u;
+    a.aligned = (n % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % vec_align == 0);
+    const float cs = value_scale32(h->s);
+
+    if (f16) {
+        if (!accumulate) {
+            if ((e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");
+        }
+        if (rows == 0) return SK_OK;
+        a.SA = SA;
+        a.ldsa = ldsa;
+        a.mode = h->rounding;
+        a.scale = cs;
+        if ((e = launch_apply(a_dtype, pl, a, st)) != hipSuccess) return hip_fail(e, "apply kernel");
+        return SK_OK;
+    }
+    a.mode = 0;
+    if (scale_is_pow2(h->s) || !accumulate) {
+        // FP32 partials go straight into SA; a non-power-of-two scale is applied
+        // once to the finished sum so the result has a single final rounding.
+        if (!accumulate) {
+            if ((e = launch_fill(SA, 4, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");
+        }
+        if (rows == 0) return SK_OK;
+        a.SA = SA;
+        a.ldsa = ldsa;
+        a.scale = scale_is_pow2(h->s) ? cs : 1.0f;
+        if ((e = launch_apply(a_dtype, pl, a, st)) != hipSuccess) return hip_fail(e, "apply kernel");
+        if (!scale_is_pow2(h->s)) {
+            if ((e = launch_scale((float*)SA, h->d, n, ldsa, nullptr, cs, 0, st)) != hipSuccess)
+                return hip_fail(e, "scale kernel");
+        }
+        return SK_OK;
+    }
+    // Accumulating with a non-power-of-two scale: sum into a workspace, then
+    // SA += fl32(c_s * sum).
+    if (rows == 0) return SK_OK;
+    const size_t need = (size_t)h->d * (size_t)n;
+    if (h->ws_floats < need) {
+        if (h->ws) (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_floats = 0;
+        if ((e = hipMalloc((void**)&h->ws, need * sizeof(float))) != hipSuccess)
+            return set_error(SK_ENOMEM, "workspace of %zu floats: %s", need, hipGetErrorString(e));
+        h->ws_floats = need;
+    }
+    if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+    a.SA = h->ws;
+    a.ldsa = n;
+    a.scale = 1.0f;
+    if ((e = launch_apply(a_dtype, pl, a, st)) != hipSuccess) return hip_fail(e, "apply kernel");
+    if ((e = launch_scale((float*)SA, h->d, n, ldsa, h->ws, cs, 1, st)) != hipSuccess)
+        return hip_fail(e, "scale kernel");
+    return SK_OK;
+}
+
+int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t* buckets, int8_t* signs, void* stream)
+{
+    if (!h) return set_error(SK_EINVAL, "handle is NULL");
+    if (row_begin < 0 || count < 0 || row_begin + count > h->m)
+        return set_error(SK_EINVAL, "rows [%lld, %lld) outside m = %lld", (long long)row_begin,
+                         (long long)(row_begin + count), (long long)h->m);
+    if (count > 0 && (!buckets || !signs)) return set_error(SK_EINVAL, "NULL output");
+    if (count == 0) return SK_OK;
+    hipError_t e = launch_hash(h->seed, h->d, h->s, row_begin, count, buckets, signs, (hipStream_t)stream);
+    return e == hipSuccess ? SK_OK : hip_fail(e, "hash kernel");
+}
+
+int sketch_quantize(int32_t mode, const float* x, uint16_t* out, int64_t count, uint64_t seed, uint32_t epoch,
+                    uint64_t site0, void* stream)
+{
+    if (mode < SK_ACC_F16_RN || mode > SK_ACC_F16_DITHER) return set_error(SK_EINVAL, "mode %d is not FP16", mode);
+    if (count < 0) return set_error(SK_EINVAL, "count < 0");
+    if (count > 0 && (!x || !out)) return set_error(SK_EINVAL, "NULL array");
+    if (count == 0) return SK_OK;
+    hipError_t e = launch_quantize(mode, x, out, count, seed, epoch, site0, (hipStream_t)stream);
+    return e == hipSuccess ? SK_OK : hip_fail(e, "quantize kernel");
+}
+
+}  // extern "C"

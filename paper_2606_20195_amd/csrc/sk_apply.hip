@@ -1,0 +1,488 @@
+// sketch_apply kernels for gfx950.
+//
+// SA = S * A with S a SparseStack operator (paper Section 2.2; s = 1 is
+// CountSketch), formed by scattering every row of A into its s hashed target
+// rows (Section 4.1).  The paper does one global atomic per contribution;
+// here each workgroup accumulates an FP32 partial of its rows in LDS and adds
+// it into SA once (FP32 atomics, or after FP16 quantisation with the rounding
+// rules of Section 4.2, packed FP16 atomics).
+//
+// Decomposition.  A workgroup owns one unit of consecutive rows, one tile of
+// 32 columns and a group of BG SparseStack blocks; its LDS partial holds
+// BG * (d/s) bucket rows of 32 FP32 values.  Each wave streams 64-row tiles:
+// lane (k, q) = (lane / 16, lane % 16) handles row slot k and column pair
+// 2q, 2q+1, so one wave instruction covers 4 rows of 64 contiguous bytes
+// (FP16) or 128 bytes (FP32).  Lane (k, q) also hashes row 4q + k of the
+// tile; in group g the 16 lanes of DPP row k read that row's bucket offsets
+// and signs from lane (k, g) with a row_newbcast DPP broadcast, so the hash is
+// computed once per row and no LDS traffic is spent distributing it.
+//
+// Bank-conflict-free scatter.  In instruction jj the lanes of slot k update
+// local block (jj + k) mod BG, so the four slots of a wave instruction hit
+// four different blocks.  Block lb's bucket rows start at an LDS word
+// offset congruent to 32*(lb & 1) + ((lb >> 1) & 1) modulo 64, so with 64
+// banks the four slots' even (then odd) columns land on four disjoint
+// 16-bank sets whatever the buckets are.
+#include <type_traits>
+
+#include "sk_device.hpp"
+#include "sk_internal.hpp"
+
+namespace sk {
+namespace {
+
+constexpr int kNT = 32;     // columns per workgroup tile
+constexpr int kTile = 64;   // rows per wave tile
+constexpr int kGroups = 16; // wave instructions (4 rows each) per tile
+
+template <int BG>
+__host__ __device__ constexpr uint32_t lds_row(uint32_t lb, uint32_t o, uint32_t W)
+{
+    return BG == 1 ? o * kNT
+                   : (lb >> 1) * (W * 64u + 64u) + o * 64u + 32u * (lb & 1u) + ((lb >> 1) & 1u);
+}
+
+template <int BG>
+__host__ __device__ constexpr size_t lds_words(uint32_t W)
+{
+    return BG == 1 ? (size_t)W * kNT : (size_t)(BG / 2) * ((size_t)W * 64u + 64u);
+}
+
+// Raw storage of one lane's column pair and its conversion to FP32.
+template <typename AT> struct PairRaw;
+template <> struct PairRaw<float> { float2 v; };
+template <> struct PairRaw<__half> { uint32_t v; };
+template <> struct PairRaw<__hip_bfloat16> { uint32_t v; };
+
+__device__ __forceinline__ void to_f32(const PairRaw<float>& r, float& lo, float& hi)
+{
+    lo = r.v.x;
+    hi = r.v.y;
+}
+__device__ __forceinline__ void to_f32(const PairRaw<__half>& r, float& lo, float& hi)
+{
+    lo = __half2float(__ushort_as_half((unsigned short)(r.v & 0xFFFFu)));
+    hi = __half2float(__ushort_as_half((unsigned short)(r.v >> 16)));
+}
+__device__ __forceinline__ void to_f32(const PairRaw<__hip_bfloat16>& r, float& lo, float& hi)
+{
+    lo = __uint_as_float(r.v << 16);
+    hi = __uint_as_float(r.v & 0xFFFF0000u);
+}
+
+// Buffer loads of the lane's column pair (columns c and c+1 of one row).  The
+// resource covers exactly the workgroup's unit of rows, so loads of rows past
+// its end return zero.  VEC: one vector load (needs even n and lda and an
+// aligned base); otherwise two scalar loads, the second `d1` elements further
+// (1, or 0 when c+1 is past the last column; such values only reach LDS
+// columns that are never flushed).
+template <bool VEC, typename AT>
+__device__ __forceinline__ PairRaw<AT> load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so, uint32_t d1);
+
+template <>
+__device__ __forceinline__ PairRaw<float> load_pair<true, float>(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so,
+                                                                 uint32_t)
+{
+    PairRaw<float> r;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, 0);
+    r.v = __builtin_bit_cast(float2, v);
+    return r;
+}
+template <>
+__device__ __forceinline__ PairRaw<float> load_pair<false, float>(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so,
+                                                                  uint32_t d1)
+{
+    PairRaw<float> r;
+    r.v.x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)vo, (int)so, 0));
+    r.v.y = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(vo + 4u * d1), (int)so, 0));
+    return r;
+}
+template <bool VEC, typename AT>
+__device__ __forceinline__ PairRaw<AT> load_pair16(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so, uint32_t d1)
+{
+    PairRaw<AT> r;
+    if constexpr (VEC) {
+        r.v = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vo, (int)so, 0);
+    } else {
+        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)vo, (int)so, 0);
+        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)(vo + 2u * d1), (int)so, 0);
+        r.v = lo | (hi << 16);
+    }
+    return r;
+}
+template <>
+__device__ __forceinline__ PairRaw<__half> load_pair<true, __half>(__amdgpu_buffer_rsrc_t rs, uint32_t vo,
+                                                                   uint32_t so, uint32_t d1)
+{
+    return load_pair16<true, __half>(rs, vo, so, d1);
+}
+template <>
+__device__ __forceinline__ PairRaw<__half> load_pair<false, __half>(__amdgpu_buffer_rsrc_t rs, uint32_t vo,
+                                                                    uint32_t so, uint32_t d1)
+{
+    return load_pair16<false, __half>(rs, vo, so, d1);
+}
+template <>
+__device__ __forceinline__ PairRaw<__hip_bfloat16> load_pair<true, __hip_bfloat16>(__amdgpu_buffer_rsrc_t rs,
+                                                                                   uint32_t vo, uint32_t so,
+                                                                                   uint32_t d1)
+{
+    return load_pair16<true, __hip_bfloat16>(rs, vo, so, d1);
+}
+template <>
+__device__ __forceinline__ PairRaw<__hip_bfloat16> load_pair<false, __hip_bfloat16>(__amdgpu_buffer_rsrc_t rs,
+                                                                                    uint32_t vo, uint32_t so,
+                                                                                    uint32_t d1)
+{
+    return load_pair16<false, __hip_bfloat16>(rs, vo, so, d1);
+}
+
+
+// row_newbcast:G -- every lane of each 16-lane row takes lane G of that row.
+template <int G>
+__device__ __forceinline__ uint32_t bcast16(uint32_t v)
+{
+    // bound_ctrl set and old = 0 let the compiler fold the move into the consumer
+    // (v_add_u32_dpp / v_xor_b32_dpp); no lane is out of range for this pattern.
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 + G, 0xF, 0xF, true);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// FP32 input doubles the registers of the load pipeline, so its kernels are
+// built for 8 waves per workgroup (the same bytes in flight as 16 FP16 waves).
+template <typename AT>
+constexpr int kMaxThreads = sizeof(AT) == 4 ? 512 : 1024;
+
+template <typename AT, int BG, bool VEC>
+__global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
+{
+    extern __shared__ float lds[];
+    const int nwaves = (int)(blockDim.x >> 6);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+
+    const int per_unit = p.col_tiles * p.bgroups;
+    int unit, t;
+    if (p.xcd_remap) {
+        // Consecutive workgroup ids go to different XCDs; give all tiles of a
+        // unit the same id modulo 8 so they read the unit's rows through one L2.
+        const int x = (int)(blockIdx.x & 7u), sidx = (int)(blockIdx.x >> 3);
+        unit = (sidx / per_unit) * 8 + x;
+        t = sidx % per_unit;
+    } else {
+        unit = (int)blockIdx.x / per_unit;
+        t = (int)blockIdx.x % per_unit;
+    }
+    const int ct = t % p.col_tiles;
+    const int bgi = t / p.col_tiles;
+    const int64_t r_begin = (int64_t)unit * p.chunk_rows;
+    const int64_t r_end = min(r_begin + (int64_t)p.chunk_rows, p.rows);
+    const int c0 = ct * kNT;
+    const uint32_t j0 = (uint32_t)bgi * BG;
+    const uint32_t W = p.W;
+
+    {
+        const size_t nw = lds_words<BG>(W);
+        float4* l4 = (float4*)lds;
+        for (size_t e = threadIdx.x; e < nw / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+
+    const int k = lane >> 4;                 // row slot within a wave instruction
+    const int q = lane & 15;                 // column pair within the tile
+    const int col = c0 + 2 * q;
+    // Lanes past the last column read columns 0 and 1 of their row; what they
+    // add lands in LDS columns >= n, which are never flushed.
+    const int colc = (col < p.n) ? col : 0;
+    const uint32_t d1 = (colc + 1 < p.n) ? 1u : 0u;
+    const uint32_t laneoff = (uint32_t)(2 * q) * 4u;
+    const int64_t span = r_end - r_begin;
+    const int64_t ntiles = span > 0 ? (span + kTile - 1) / kTile : 0;
+
+    // One buffer resource per workgroup covering its unit (the planner keeps a
+    // unit below 2 GiB); vector offset = the lane's row and column, scalar
+    // offset = the row group within the tile.
+    constexpr uint32_t esz = (uint32_t)sizeof(AT);
+    const AT* ubase = (const AT*)p.A + r_begin * p.lda;
+    const uint32_t nrec = (uint32_t)(span > 0 ? span * p.lda * (int64_t)esz : 0);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)ubase, (short)0, (int)nrec, 0x00020000);
+    const uint32_t lane_vo = ((uint32_t)k * (uint32_t)p.lda + (uint32_t)colc) * esz;
+    const uint32_t gstep = 4u * (uint32_t)p.lda * esz;
+    const uint32_t tstep = (uint32_t)kTile * (uint32_t)p.lda * esz;
+
+    auto load_tile = [&](PairRaw<AT> (&buf)[kGroups], int64_t tile) {
+        const uint32_t vo = lane_vo + (uint32_t)tile * tstep;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) buf[g] = load_pair<VEC, AT>(rsrc, vo, (uint32_t)g * gstep, d1);
+    };
+
+    // Lane (k, q) hashes row 4q + k of the tile and keeps, for instruction jj,
+    // the LDS byte offset and sign mask of local block (jj + k) mod BG.
+    auto hash_tile = [&](uint32_t (&hoff)[BG], uint32_t (&hsgn)[BG], int64_t tile) {
+        const uint64_t grow = (uint64_t)(p.row_offset + r_begin + tile * kTile + 4 * q + k);
+        uint4 w4a = row_words(grow, j0 >> 2, p.k0, p.k1);
+        uint4 w4b = w4a;
+        if (BG == 8 || (BG > 1 && ((j0 & 3u) + BG > 4u))) w4b = row_words(grow, (j0 >> 2) + 1u, p.k0, p.k1);
+#pragma unroll
+        for (int jj = 0; jj < BG; ++jj) {
+            const uint32_t lb = (uint32_t)(jj + k) & (uint32_t)(BG - 1);
+            const uint32_t wi = (j0 & 3u) + lb;            // word index from the first call
+            const uint32_t w = (wi < 4u) ? word_of(w4a, wi) : word_of(w4b, wi - 4u);
+            hoff[jj] = lds_row<BG>(lb, bucket_in_block(w, W), W) * 4u;
+            hsgn[jj] = w << 31;
+        }
+    };
+
+    auto scatter_tile = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                            const uint32_t (&hsgn)[BG]) {
+        static_for<0, kGroups>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            float lo, hi;
+            to_f32(buf[g], lo, hi);
+#pragma unroll
+            for (int jj = 0; jj < BG; ++jj) {
+                const uint32_t off = bcast16<g>(hoff[jj]) + laneoff;
+                const uint32_t sg = bcast16<g>(hsgn[jj]);
+                float* dst = (float*)__builtin_assume_aligned((char*)lds + off, 4);
+                __hip_atomic_fetch_add(dst, __uint_as_float(__float_as_uint(lo) ^ sg),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(dst + 1, __uint_as_float(__float_as_uint(hi) ^ sg),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        });
+    };
+
+    PairRaw<AT> bufA[kGroups], bufB[kGroups];
+    uint32_t offA[BG], sgnA[BG], offB[BG], sgnB[BG];
+    int64_t tile = wave;
+    if (tile < ntiles) {
+        load_tile(bufA, tile);
+        hash_tile(offA, sgnA, tile);
+    }
+    // Software pipeline: the next tile's loads are in flight while the current
+    // tile is scattered; the loop is unrolled twice to ping-pong the buffers.
+    // Rows past the unit's end load as zero and add nothing.
+    while (tile < ntiles) {
+        int64_t nxt = tile + nwaves;
+        if (nxt < ntiles) load_tile(bufB, nxt);
+        scatter_tile(bufA, offA, sgnA);
+        if (nxt >= ntiles) break;
+        hash_tile(offB, sgnB, nxt);
+        tile = nxt;
+        nxt = tile + nwaves;
+        if (nxt < ntiles) load_tile(bufA, nxt);
+        scatter_tile(bufB, offB, sgnB);
+        if (nxt >= ntiles) break;
+        hash_tile(offA, sgnA, nxt);
+        tile = nxt;
+    }
+    __syncthreads();
+
+    // ---- flush the partial into SA -----------------------------------------
+    const int64_t r0g = p.row_offset + r_begin;             // first global row of the unit
+    if (p.mode == 0) {
+        float* SA = (float*)p.SA;
+        const uint32_t total = (uint32_t)BG * W * kNT;
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const uint32_t c = e % kNT, o = (e / kNT) % W, lb = e / (kNT * W);
+            const int cc = c0 + (int)c;
+            if (cc >= p.n) continue;
+            const float v = lds[lds_row<BG>(lb, o, W) + c] * p.scale;
+            const int64_t b = (int64_t)(j0 + lb) * W + o;
+            unsafeAtomicAdd(SA + b * p.ldsa + cc, v);
+        }
+    } else {
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        uint16_t* SA = (uint16_t*)p.SA;
+        const uint32_t total = (uint32_t)BG * W * (kNT / 2);
+        const uint64_t dn = (uint64_t)p.d * (uint64_t)p.n;
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const uint32_t cp = e % (kNT / 2), o = (e / (kNT / 2)) % W, lb = e / ((kNT / 2) * W);
+            const int cc = c0 + 2 * (int)cp;
+            if (cc >= p.n) continue;
+            const uint32_t li = lds_row<BG>(lb, o, W) + 2 * cp;
+            const int64_t b = (int64_t)(j0 + lb) * W + o;
+            const uint64_t site = (uint64_t)r0g * dn + (uint64_t)b * (uint64_t)p.n + (uint64_t)cc;
+            uint32_t u0 = 0, u1 = 0;
+            if (p.mode >= 2) {
+                u0 = round_bits(site, p.epoch, p.k0, p.k1);
+                u1 = round_bits(site + 1, p.epoch, p.k0, p.k1);
+            }
+            const uint16_t h0 = quantize(p.mode, lds[li] * p.scale, u0);
+            // -0.0 leaves the neighbouring half unchanged (x + -0 == x for every x)
+            const uint16_t h1 = (cc + 1 < p.n) ? quantize(p.mode, lds[li + 1] * p.scale, u1)
+                                               : (uint16_t)0x8000u;
+            const uint32_t packed = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            h2 hv = __builtin_bit_cast(h2, packed);
+            __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * p.ldsa + cc), hv);
+        }
+    }
+}
+
+__global__ void fill_kernel(void* p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld)
+{
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / cols, c = e % cols;
+        if (elem_bytes == 4) ((float*)p)[r * ld + c] = 0.0f;
+        else ((uint16_t*)p)[r * ld + c] = 0;
+    }
+}
+
+// SA = (accumulate ? SA : 0) + fl32(c * ws), ws a d x n FP32 array (ld n).
+// Without a workspace (ws == SA) the scale is applied in place.
+__global__ void scale_kernel(float* SA, int64_t d, int64_t n, int64_t ldsa, const float* ws, float c,
+                             int accumulate)
+{
+    const int64_t total = d * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n, col = e % n;
+        float* dst = SA + r * ldsa + col;
+        if (ws == nullptr) {
+            *dst = c * *dst;
+        } else {
+            const float v = c * ws[r * n + col];
+            *dst = accumulate ? *dst + v : v;
+        }
+    }
+}
+
+__global__ void hash_kernel(uint32_t k0, uint32_t k1, uint32_t W, int32_t s, int64_t row_begin,
+                            int64_t count, int32_t* buckets, int8_t* signs)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = (uint64_t)(row_begin + t);
+        uint4 w4 = make_uint4(0, 0, 0, 0);
+        for (int32_t j = 0; j < s; ++j) {
+            if ((j & 3) == 0) w4 = row_words(i, (uint32_t)j >> 2, k0, k1);
+            const uint32_t w = word_of(w4, (uint32_t)j & 3u);
+            buckets[t * s + j] = (int32_t)((uint32_t)j * W + bucket_in_block(w, W));
+            signs[t * s + j] = (w & 1u) ? (int8_t)-1 : (int8_t)1;
+        }
+    }
+}
+
+__global__ void quantize_kernel(int mode, const float* x, uint16_t* out, int64_t count, uint32_t k0,
+                                uint32_t k1, uint32_t epoch, uint64_t site0)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t u = (mode >= 2) ? round_bits(site0 + (uint64_t)t, epoch, k0, k1) : 0u;
+        out[t] = quantize(mode, x[t], u);
+    }
+}
+
+template <typename AT, int BG, bool VEC>
+hipError_t launch_typed(const Plan& plan, const ApplyArgs& a, hipStream_t st)
+{
+    static size_t attr_bytes = 0;
+    auto kern = apply_kernel<AT, BG, VEC>;
+    if (plan.lds_bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)plan.lds_bytes);
+        if (e != hipSuccess) return e;
+        attr_bytes = plan.lds_bytes;
+    }
+    const int64_t grid = plan.units * (int64_t)plan.col_tiles * plan.bgroups;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)(64 * plan.waves)), plan.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+template <typename AT, bool VEC>
+hipError_t launch_bg(const Plan& plan, const ApplyArgs& a, hipStream_t st)
+{
+    switch (plan.bg) {
+    case 1: return launch_typed<AT, 1, VEC>(plan, a, st);
+    case 2: return launch_typed<AT, 2, VEC>(plan, a, st);
+    case 4: return launch_typed<AT, 4, VEC>(plan, a, st);
+    case 8: return launch_typed<AT, 8, VEC>(plan, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename AT>
+hipError_t launch_vec(const Plan& plan, const ApplyArgs& a, hipStream_t st)
+{
+    return a.aligned ? launch_bg<AT, true>(plan, a, st) : launch_bg<AT, false>(plan, a, st);
+}
+
+unsigned grid_for(int64_t work, int threads)
+{
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+int apply_max_waves(int32_t a_dtype)
+{
+    return (a_dtype == SK_F32 ? kMaxThreads<float> : kMaxThreads<__half>) / 64;
+}
+
+size_t apply_lds_bytes(int32_t bg, int64_t W)
+{
+    switch (bg) {
+    case 1: return lds_words<1>((uint32_t)W) * 4;
+    case 2: return lds_words<2>((uint32_t)W) * 4;
+    case 4: return lds_words<4>((uint32_t)W) * 4;
+    case 8: return lds_words<8>((uint32_t)W) * 4;
+    default: return (size_t)-1;
+    }
+}
+
+hipError_t launch_apply(int a_dtype, const Plan& plan, const ApplyArgs& a, hipStream_t st)
+{
+    switch (a_dtype) {
+    case SK_F32: return launch_vec<float>(plan, a, st);
+    case SK_F16: return launch_vec<__half>(plan, a, st);
+    case SK_BF16: return launch_vec<__hip_bfloat16>(plan, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill(void* p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(rows * cols, 256)), dim3(256), 0, st, p, elem_bytes, rows,
+                       cols, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(float* SA, int64_t d, int64_t n, int64_t ldsa, const float* ws, float c, int accumulate,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(d * n, 256)), dim3(256), 0, st, SA, d, n, ldsa, ws, c,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, int64_t count, int32_t* buckets,
+                       int8_t* signs, hipStream_t st)
+{
+    hipLaunchKernelGGL(hash_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), (uint32_t)(d / s), s, row_begin, count, buckets, signs);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(int mode, const float* x, uint16_t* out, int64_t count, uint64_t seed, uint32_t epoch,
+                           uint64_t site0, hipStream_t st)
+{
+    hipLaunchKernelGGL(quantize_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, mode, x, out, count,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), epoch, site0);
+    return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,75 @@
+// Host-side internals shared by the C ABI and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+
+#include "../../include/sketch.h"
+
+struct sk_sketch {
+    int64_t m = 0, d = 0;
+    int32_t s = 0;
+    uint64_t seed = 0;
+    int32_t rounding = 0;
+    bool forced = false;
+    sk_schedule sched{};
+    // FP32 workspace for SK_ACCUMULATE when 1/sqrt(s) is not a power of two
+    float *ws = nullptr;
+    size_t ws_floats = 0;
+};
+
+namespace sk {
+
+int set_error(int code, const char *fmt, ...);
+
+struct DeviceInfo {
+    int device = -1;
+    int cus = 0;
+    size_t lds_max = 0;
+};
+int device_info(DeviceInfo *out);
+
+// Resolved launch plan of one apply call.
+struct Plan {
+    int32_t bg = 0;          // blocks per workgroup
+    int32_t bgroups = 0;     // s / bg
+    int32_t col_tiles = 0;   // ceil(n / 32)
+    int32_t waves = 0;
+    int32_t chunk_rows = 0;
+    int64_t units = 0;
+    int32_t xcd_remap = 0;
+    size_t lds_bytes = 0;
+};
+
+size_t apply_lds_bytes(int32_t bg, int64_t W);
+int make_plan(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo &dev,
+              Plan *out);
+int apply_max_waves(int32_t a_dtype);
+
+struct ApplyArgs {
+    const void *A;
+    int64_t lda, rows, row_offset;
+    void *SA;
+    int64_t ldsa;
+    int32_t n, d, s;
+    uint32_t W;
+    uint32_t k0, k1;
+    int32_t chunk_rows, col_tiles, bgroups;
+    int32_t mode;        // 0: FP32 atomics, 1 RN, 2 SR, 3 dither
+    float scale;         // multiplier of each flushed partial
+    uint32_t epoch;
+    int32_t xcd_remap;
+    int32_t aligned;     // vector loads allowed
+};
+
+hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
+hipError_t launch_fill(void *p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+hipError_t launch_scale(float *SA, int64_t d, int64_t n, int64_t ldsa, const float *ws, float c,
+                        int accumulate, hipStream_t st);
+hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, int64_t count,
+                       int32_t *buckets, int8_t *signs, hipStream_t st);
+hipError_t launch_quantize(int mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
+                           uint32_t epoch, uint64_t site0, hipStream_t st);
+
+}  // namespace sk

@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, and rejects invalid calls with the documented codes before any HIP
+call is made (fake, never dereferenced pointers are used here)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2606_20195_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x10000)      # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(sketch_\w+|sk_server_\w+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert {"sketch_create", "sketch_apply", "sketch_destroy"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(_lib.EXPORTS) <= names
+
+
+def test_version(lib):
+    assert lib.sketch_version() == 101
+
+
+def _create(lib, m=1000, d=64, s=4, rounding=0):
+    h = ctypes.c_void_p()
+    rc = lib.sketch_create(m, d, s, 0, rounding, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validation(lib):
+    assert _create(lib, m=0)[0] == _lib.EINVAL
+    assert _create(lib, d=0)[0] == _lib.EINVAL
+    assert _create(lib, s=0)[0] == _lib.EINVAL
+    assert _create(lib, s=17)[0] == _lib.EINVAL
+    assert _create(lib, d=30, s=4)[0] == _lib.EINVAL          # d % s != 0
+    assert b"multiple" in lib.sketch_last_error()
+    assert _create(lib, rounding=4)[0] == _lib.EINVAL
+    assert lib.sketch_create(10, 8, 1, 0, 0, None) == _lib.EINVAL
+    rc, h = _create(lib)
+    assert rc == 0 and h.value
+    assert lib.sketch_destroy(h) == 0
+    assert lib.sketch_destroy(None) == 0
+
+
+def test_apply_validation(lib):
+    rc, h = _create(lib, m=1000, d=64, s=4, rounding=0)
+    assert rc == 0
+    ap = lambda **kw: lib.sketch_apply(   # noqa: E731
+        kw.get("h", h), kw.get("A", FAKE), kw.get("dt", 0), kw.get("rows", 100), kw.get("n", 8),
+        kw.get("lda", 8), kw.get("off", 0), kw.get("SA", FAKE), kw.get("ldsa", 8), kw.get("flags", 0),
+        0, None)
+    assert ap(h=None) == _lib.EINVAL
+    assert ap(dt=7) == _lib.EINVAL
+    assert ap(rows=-1) == _lib.EINVAL
+    assert ap(n=0) == _lib.EINVAL
+    assert ap(lda=7) == _lib.EINVAL
+    assert ap(off=950) == _lib.EINVAL                        # past m
+    assert ap(off=-1) == _lib.EINVAL
+    assert ap(SA=None) == _lib.EINVAL
+    assert ap(ldsa=4) == _lib.EINVAL
+    assert ap(A=None) == _lib.EINVAL
+    assert ap(flags=2) == _lib.EINVAL
+    assert ap(A=ctypes.c_void_p(0x10001), dt=0) == _lib.EINVAL  # misaligned FP32 A
+    lib.sketch_destroy(h)
+    rc, h16 = _create(lib, m=1000, d=64, s=4, rounding=1)
+    # FP16 SA needs 4-byte alignment and an even leading dimension
+    assert lib.sketch_apply(h16, FAKE, 1, 10, 8, 8, 0, ctypes.c_void_p(0x10002), 8, 0, 0, None) == _lib.EUNSUPPORTED
+    assert lib.sketch_apply(h16, FAKE, 1, 10, 8, 8, 0, FAKE, 9, 0, 0, None) == _lib.EUNSUPPORTED
+    lib.sketch_destroy(h16)
+
+
+def test_schedule_validation(lib):
+    rc, h = _create(lib)
+    S = _lib.Schedule
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(100, 0, 0, 1))) == _lib.EINVAL    # not a multiple of 64
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 3, 0, 1))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 32, 1))) == _lib.EINVAL
+    bad = S(0, 0, 0, 1)
+    bad.reserved[2] = 1
+    assert lib.sketch_set_schedule(h, ctypes.byref(bad)) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(4096, 4, 8, 0))) == 0
+    assert lib.sketch_set_schedule(h, None) == 0
+    lib.sketch_destroy(h)
+
+
+def test_debug_exports_validation(lib):
+    rc, h = _create(lib, m=100)
+    assert lib.sketch_hash(h, 90, 20, FAKE, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_hash(h, 0, 5, None, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_hash(h, 0, 0, None, None, None) == 0              # empty range: nothing to do
+    assert lib.sketch_quantize(0, FAKE, FAKE, 4, 0, 0, 0, None) == _lib.EINVAL   # FP32 is not a rounding rule
+    assert lib.sketch_quantize(2, FAKE, FAKE, -1, 0, 0, 0, None) == _lib.EINVAL
+    assert lib.sketch_quantize(2, None, FAKE, 3, 0, 0, 0, None) == _lib.EINVAL
+    assert lib.sketch_quantize(2, None, None, 0, 0, 0, 0, None) == 0
+    lib.sketch_destroy(h)

@@ -1,0 +1,221 @@
+"""Parity of the HIP sketch_apply path with the oracle (needs an MI355X).
+
+Bars: bit-exact for the hash and the quantisers; bit-exact FP32 results on
+integer-valued A (every partial sum exact); relative Frobenius error <= 1e-5
+for FP32 accumulation and <= 4e-3 for the FP16 modes against the FP64 oracle;
+bit-exact FP16 results when one unit covers all rows (one quantisation per
+entry, no FP16 additions).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import model, native, quant
+from oracle.sketch import apply_f64, distortion, hash_rows, orthonormal_basis
+from paper_2606_20195_amd import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch,
+                                  quantize)
+
+pytestmark = pytest.mark.gpu
+
+TORCH_DT = {np.float32: torch.float32, np.float16: torch.float16}
+
+
+def to_dev(A, dtype=None, pad=0):
+    """Device copy of A (optionally stored as bfloat16 / with lda = n + pad)."""
+    A = np.ascontiguousarray(A)
+    rows, n = A.shape
+    t = torch.from_numpy(A.astype(np.float32) if dtype == torch.bfloat16 else A)
+    if dtype is not None:
+        t = t.to(dtype)
+    if pad:
+        big = torch.zeros((rows, n + pad), dtype=t.dtype)
+        big[:, :n] = t
+        return big.cuda()[:, :n]
+    return t.cuda()
+
+
+def run(A_dev, m, d, s, seed, rounding, row_offset=0, epoch=0, sched=None):
+    sk = Sketch(m, d, s, seed, rounding)
+    if sched:
+        sk.set_schedule(**sched)
+    SA = sk.apply(A_dev, row_offset=row_offset, epoch=epoch)
+    torch.cuda.synchronize()
+    return SA.float().cpu().numpy().astype(np.float64) if rounding else SA.cpu().numpy()
+
+
+def rel_fro(got, ref):
+    return float(np.linalg.norm(np.asarray(got, np.float64) - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("m,d,s,seed,r0,count", [
+    (1 << 20, 256, 4, 0, 0, 5000), (1 << 40, 1024, 8, 2 ** 63 + 5, 2 ** 33 + 7, 3000),
+    (100000, 30, 3, 7, 99000, 1000), (4096, 1024, 1, 1, 0, 4096), (5000, 64, 16, 9, 17, 2000)])
+def test_hash_is_bit_exact(m, d, s, seed, r0, count):
+    b, g = Sketch(m, d, s, seed).hash(r0, count)
+    rb, rg = hash_rows(seed, np.arange(r0, r0 + count, dtype=np.uint64), d, s)
+    assert np.array_equal(b.cpu().numpy(), rb)
+    assert np.array_equal(g.cpu().numpy(), rg)
+
+
+def _quant_inputs():
+    g = np.random.default_rng(3)
+    x = (g.standard_normal(2500) * np.exp2(g.integers(-28, 17, 2500))).astype(np.float32)
+    edge = np.array([0.0, -0.0, 1.0, 65504.0, 65519.0, 65520.0, 70000.0, -70000.0, 2 ** -24, 3 * 2 ** -25,
+                     -2 ** -26, 1 / np.sqrt(8), np.inf, -np.inf, 2 ** -14, 2 ** -14 * (1 - 2 ** -10)],
+                    dtype=np.float32)
+    return np.concatenate([edge, x])
+
+
+@pytest.mark.parametrize("mode", [ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER])
+def test_quantizers_are_bit_exact(mode):
+    x = _quant_inputs()
+    seed, epoch, site0 = 0x0123456789ABCDEF, 77, 2 ** 40 + 3
+    got = quantize(mode, torch.from_numpy(x).cuda(), seed, epoch, site0).cpu().numpy().view(np.uint16)
+    u = model.round_u24(seed, epoch, np.uint64(site0) + np.arange(x.size, dtype=np.uint64))
+    ref = quant.quantize(mode, x, u).view(np.uint16)
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:10]
+
+
+INT_CASES = [
+    # rows, n, d, s, dtype, pad, row_offset
+    (16384, 32, 256, 4, np.float32, 0, 0),
+    (16384, 32, 256, 1, np.float32, 0, 0),
+    (16384, 32, 256, 8, np.float32, 0, 0),
+    (16384, 32, 256, 2, np.float32, 0, 0),
+    (6000, 64, 128, 4, np.float16, 0, 12345),
+    (6000, 64, 128, 4, torch.bfloat16, 0, 0),
+    (3001, 37, 64, 4, np.float32, 3, 5),      # odd n, padded rows: scalar-load path
+    (3001, 37, 64, 4, np.float16, 0, 5),      # odd n, odd lda
+    (2500, 100, 96, 3, np.float32, 2, 0),     # s = 3: one block per workgroup
+    (9000, 16, 1024, 16, np.float16, 0, 0),   # two groups of 8 blocks
+    (70, 5, 8, 8, np.float32, 0, 0),          # d = s: one bucket per block
+]
+
+
+@pytest.mark.parametrize("rows,n,d,s,dt,pad,r0", INT_CASES)
+def test_fp32_integer_inputs_are_bit_exact(rows, n, d, s, dt, pad, r0):
+    A = workloads.integers(rows, n, seed=rows + n, lim=8)
+    dev = to_dev(A.astype(np.float32) if dt is torch.bfloat16 else A.astype(dt),
+                 torch.bfloat16 if dt is torch.bfloat16 else None, pad)
+    got = run(dev, rows + r0 + 11, d, s, 42, ACC_F32, row_offset=r0)
+    ref = model.apply_f32_exact_int(A, d, s, 42, row_offset=r0)
+    assert np.array_equal(got, ref), (np.flatnonzero(got != ref)[:8], got.ravel()[:4], ref.ravel()[:4])
+
+
+@pytest.mark.parametrize("s", [1, 4, 8])
+def test_fp32_gaussian_small_case(s):
+    A = workloads.small_case()
+    got = run(to_dev(A), A.shape[0], 256, s, 0, ACC_F32)
+    ref = apply_f64(A, 256, s, 0)
+    assert rel_fro(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", [ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER])
+@pytest.mark.parametrize("s", [1, 4])
+def test_fp16_modes_small_case(mode, s):
+    A = workloads.small_case()
+    got = run(to_dev(A), A.shape[0], 256, s, 0, mode, epoch=3)
+    ref = apply_f64(A, 256, s, 0)
+    assert rel_fro(got, ref) <= 4e-3
+
+
+@pytest.mark.parametrize("mode", [ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER])
+@pytest.mark.parametrize("s,d", [(8, 256), (4, 128), (1, 64)])
+def test_fp16_one_unit_is_bit_exact(mode, s, d):
+    rows, n = 4096, 40
+    A = workloads.integers(rows, n, seed=5, lim=6)
+    got16 = Sketch(rows + 100, d, s, 9, mode)
+    got16.set_schedule(chunk_rows=rows)
+    SA = got16.apply(to_dev(A), row_offset=100, epoch=11)
+    torch.cuda.synchronize()
+    got = SA.cpu().numpy().view(np.uint16)
+    ref = model.apply_f16_model(A, d, s, 9, mode, 11, chunk_rows=rows, row_offset=100).view(np.uint16)
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:10]
+
+
+@pytest.mark.parametrize("s", [4, 8, 2])
+def test_row_shards_accumulate_to_the_whole(s):
+    rows, n, d = 20000, 48, 256
+    A = workloads.integers(rows, n, seed=8)
+    dev = to_dev(A)
+    sk = Sketch(rows, d, s, 3, ACC_F32)
+    whole = sk.apply(dev).cpu().numpy()
+    SA = torch.full((d, n), 5.0, device="cuda")
+    SA = sk.apply(dev[:7000], SA=SA)                     # overwrite, not add
+    SA = sk.apply(dev[7000:15000], SA=SA, row_offset=7000, accumulate=True)
+    SA = sk.apply(dev[15000:], SA=SA, row_offset=15000, accumulate=True)
+    torch.cuda.synchronize()
+    if s in (1, 4, 16):        # power-of-two scale: the shard sums are exact too
+        assert np.array_equal(SA.cpu().numpy(), whole)
+    else:
+        # each shard is scaled (rounded) once, then the shards are added
+        parts = [model.apply_f32_exact_int(A[a:b], d, s, 3, row_offset=a)
+                 for a, b in [(0, 7000), (7000, 15000), (15000, rows)]]
+        ref = ((parts[0] + parts[1]).astype(np.float32) + parts[2]).astype(np.float32)
+        assert np.array_equal(SA.cpu().numpy(), ref)
+
+
+def test_empty_input_clears_sa():
+    for mode in (ACC_F32, ACC_F16_RN):
+        sk = Sketch(100, 64, 4, 0, mode)
+        SA = torch.full((64, 8), 3.0, device="cuda", dtype=sk.out_dtype)
+        sk.apply(torch.zeros((0, 8), device="cuda"), SA=SA)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(SA).item() == 0
+        SA.fill_(3.0)
+        sk.apply(torch.zeros((0, 8), device="cuda"), SA=SA, accumulate=True)
+        torch.cuda.synchronize()
+        assert torch.all(SA == 3.0).item()
+
+
+def test_distortion_matches_oracle_small_case():
+    A = workloads.small_case()
+    U = orthonormal_basis(A)
+    got = run(to_dev(U.astype(np.float32)), U.shape[0], 256, 4, 0, ACC_F32)
+    eta_gpu = distortion(got)
+    eta_ref = distortion(apply_f64(U.astype(np.float32), 256, 4, 0))
+    assert abs(eta_gpu - eta_ref) < 1e-5
+    assert 0.1 < eta_ref < 0.9
+
+
+def test_sr_is_unbiased_and_dither_matches_its_mean_over_epochs():
+    m, n, d, s = 65536, 64, 1024, 8
+    A = to_dev(workloads.spikes(m, n, np.float32))
+    cs = float(model.c_s32(s))
+    means = {}
+    for mode in (ACC_F16_SR, ACC_F16_DITHER, ACC_F16_RN):
+        sk = Sketch(m, d, s, 4, mode)
+        acc = torch.zeros((d, n), dtype=torch.float64, device="cuda")
+        K = 400 if mode != ACC_F16_RN else 2
+        for e in range(K):
+            acc += sk.apply(A, epoch=e).double().abs()
+        torch.cuda.synchronize()
+        vals = acc.cpu().numpy()
+        nz = vals[vals != 0] / K
+        assert nz.size == s * n            # one spike per column: s entries each
+        means[mode] = float(nz.mean())
+    sd = 8.8e-5 / np.sqrt(s * n * 400)
+    assert abs(means[ACC_F16_SR] - cs) < 5 * sd
+    assert abs(means[ACC_F16_RN] - cs) > 100 * sd          # RN is biased at this value
+    assert abs(means[ACC_F16_DITHER] - float(quant.dither16_mean(np.float32(cs)))) < 5 * 2.4e-4 / np.sqrt(
+        s * n * 400)
+
+
+@pytest.mark.parametrize("dt,mode,tol", [(np.float16, ACC_F16_RN, 4e-3), (np.float32, ACC_F32, 1e-5),
+                                         (np.float16, ACC_F32, 1e-5)])
+def test_full_size_apply(dt, mode, tol):
+    A = workloads.apply_case("gaussian", dtype=dt)
+    m = A.shape[0]
+    got = run(to_dev(A), m, 1024, 4, 0, mode)
+    ref = native.sketch_f64(A, 1024, 4, 0)
+    assert rel_fro(got, ref) <= tol
+
+
+def test_full_size_coherent_and_spikes_fp16():
+    for kind in ("coherent", "spikes"):
+        A = workloads.apply_case(kind, dtype=np.float16)
+        for s in (1, 8):
+            got = run(to_dev(A), A.shape[0], 1024, s, 0, ACC_F16_RN)
+            ref = native.sketch_f64(A, 1024, s, 0)
+            assert rel_fro(got, ref) <= 4e-3, (kind, s)
