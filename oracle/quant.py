@@ -170,11 +170,21 @@ def rn32(fr):
 
 
 def fma32(a, b, c):
-    """Single-rounding FP32 fused multiply-add a*b + c, exact model."""
+    """Single-rounding FP32 fused multiply-add a*b + c, exact model.
+
+    An exactly-zero result follows IEEE 754 (round to nearest): the sum of two
+    zeros of the same sign keeps that sign, every other exact zero is +0."""
     a, b, c = (float(np.float32(v)) for v in (a, b, c))
     if any(math.isinf(v) or math.isnan(v) for v in (a, b, c)):
         return float(np.float32(a) * np.float32(b) + np.float32(c))
-    return rn32(Fraction(a) * Fraction(b) + Fraction(c))
+    exact = Fraction(a) * Fraction(b) + Fraction(c)
+    if exact == 0:
+        prod_neg = (math.copysign(1.0, a) < 0) != (math.copysign(1.0, b) < 0)
+        prod_zero = a == 0 or b == 0
+        if prod_zero and c == 0 and prod_neg and math.copysign(1.0, c) < 0:
+            return -0.0
+        return 0.0
+    return rn32(exact)
 
 
 def dither16(x, u):
@@ -183,15 +193,14 @@ def dither16(x, u):
     u = np.asarray(u, dtype=np.uint64) & np.uint64(U24)
     x, u = np.broadcast_arrays(x, u)
     y = np.empty(x.shape, dtype=np.float32)
-    xf_all = x.astype(np.float64) * DITHER_F
+    xf_all = x * np.float32(DITHER_F)                            # fl32(x * F), one FP32 multiply
     for idx in np.ndindex(x.shape):
         xv = float(x[idx])
         if math.isnan(xv) or math.isinf(xv):
             y[idx] = xv
             continue
-        t = Fraction(int(u[idx]), 2 ** 24) - Fraction(1, 2)      # exact in FP32
-        xf = rn32(Fraction(float(xf_all[idx])))                  # fl32(x * F)
-        y[idx] = np.float32(rn32(t * Fraction(xf) + Fraction(xv)))
+        t = int(u[idx]) * 2.0 ** -24 - 0.5                        # exact in FP32
+        y[idx] = np.float32(fma32(t, float(xf_all[idx]), xv))
     return rn16(y)
 
 

@@ -94,6 +94,12 @@ def test_fma32_matches_libm_fmaf():
     for _ in range(3000):
         a, b, c = (g.standard_normal(3) * np.exp2(g.integers(-30, 30, 3))).astype(np.float32)
         assert quant.fma32(a, b, c) == float(libm.fmaf(float(a), float(b), float(c)))
+    for a, b, c in [(0.0, -1.0, -0.0), (-0.0, -0.0, -0.0), (0.5, -0.0, -0.0), (-0.5, -0.0, -0.0),
+                    (0.0, 1.0, -0.0), (-2.0, 3.0, 6.0), (2.0, 3.0, -6.0), (0.0, 2.0, 0.0), (-0.0, 2.0, 0.0),
+                    (1e-30, 1e-30, -0.0), (-1e-30, 1e-30, 0.0)]:   # exact zeros and underflow
+        ref = float(libm.fmaf(a, b, c))
+        got = quant.fma32(a, b, c)
+        assert got == ref and np.signbit(got) == np.signbit(ref), (a, b, c, got, ref)
     for _ in range(1000):   # the dither's shape: t in [-1/2, 1/2), x * 2**-10, x
         x = np.float32(g.standard_normal())
         t = np.float32(int(g.integers(0, 2 ** 24)) * 2.0 ** -24 - 0.5)
