@@ -161,7 +161,84 @@ __device__ __forceinline__ void static_for(F&& f)
 template <typename AT>
 constexpr int kMaxThreads = sizeof(AT) == 4 ? 512 : 1024;
 
-template <typename AT, int BG, bool VEC>
+// Fixed-point LDS partials (the FP16 modes).
+//
+// LDS floating-point atomics are two orders of magnitude slower than integer
+// ones on this GPU, so the FP16 modes accumulate each unit exactly in integer
+// fixed point: a contribution x becomes q = round(x * 2^S) with |q| < 2^(20-c)
+// and is added as the offset-binary field B + sigma*q (B = 2^(21-c)) into one
+// 32-bit half of a 64-bit LDS word; the two columns of a lane's pair share
+// one ds_add_u64.  The conversion is a single FMA, y = x * 2^S + 2^23 + B,
+// whose low 23 bits are B + q; XOR with 0x4B000000 (sign +) or
+// 0x4B000000 | (2B - 1) (sign -) turns y's bits into the field value, the
+// negative case being B - q - 1.  A per-bucket-row counter holds the number
+// K of contributions (low 16 bits) and of negative ones N (high 16 bits), so
+// the field sum F decodes exactly to sum(sigma*q) = F - K*B + N as long as no
+// field exceeds 2^32 (K < 2^(10+c)).  S comes from the largest |x| of the
+// first tiles (one binade of headroom); the workgroup tracks the true maximum
+// and the largest K and, if either bound was broken, recomputes the unit with
+// the exact parameters.  Non-finite input falls back to FP32 LDS atomics.
+constexpr uint32_t kMagicBits = 0x4B000000u;   // bit pattern of 2^23
+
+template <int BG>
+__device__ __forceinline__ uint32_t lds_row_fixed(uint32_t lb, uint32_t o, uint32_t W)
+{
+    // 64-bit words: no one-word shift; with two 32-lane passes per wave
+    // instruction, slots 0/1 and 2/3 update blocks of opposite parity.
+    return BG == 1 ? o * kNT : (lb >> 1) * (W * 64u + 64u) + o * 64u + 32u * (lb & 1u);
+}
+
+// Largest |x| of one lane's pair so far, as sign-cleared bit patterns (monotone
+// in |x|; infinities and NaNs compare above every finite value).
+__device__ __forceinline__ uint32_t pair_mag(const PairRaw<float>& r, uint32_t m)
+{
+    return max(m, max(__float_as_uint(r.v.x) & 0x7FFFFFFFu, __float_as_uint(r.v.y) & 0x7FFFFFFFu));
+}
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+template <typename AT>
+__device__ __forceinline__ uint32_t pair_mag(const PairRaw<AT>& r, uint32_t m)
+{
+    // per-half 16-bit maximum of the magnitudes (v_pk_max_u16)
+    const u16x2 a = __builtin_bit_cast(u16x2, r.v & 0x7FFF7FFFu);
+    const u16x2 b = __builtin_bit_cast(u16x2, m);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, b));
+}
+__device__ __forceinline__ uint32_t mag16_to_f32bits(uint32_t m, bool bf16)
+{
+    const uint32_t a = max(m & 0xFFFFu, m >> 16);
+    if (bf16) return a << 16;
+    return __float_as_uint(__half2float(__ushort_as_half((unsigned short)a)));
+}
+
+struct FixedParams {
+    float scale;      // 2^S
+    float magic;      // 2^23 + B
+    uint32_t xneg;    // 0x4B000000 | (2B - 1)
+    uint32_t B;
+    int S;
+};
+
+__device__ __forceinline__ FixedParams fixed_params(int E, int c)
+{
+    FixedParams f;
+    int S = 19 - c - E;
+    S = S > 127 ? 127 : (S < -126 ? -126 : S);
+    f.S = S;
+    f.scale = __uint_as_float((uint32_t)(S + 127) << 23);
+    f.B = 1u << (21 - c);
+    f.magic = 8388608.0f + (float)f.B;
+    f.xneg = kMagicBits | (2u * f.B - 1u);
+    return f;
+}
+
+__device__ __forceinline__ int binade_of(uint32_t magbits)
+{
+    if (magbits == 0) return 0;
+    const int e = (int)((magbits >> 23) & 0xFFu) - 127;
+    return e < -126 ? -126 : e;
+}
+
+template <typename AT, int BG, bool VEC, bool FIXED>
 __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
 {
     extern __shared__ float lds[];
@@ -188,13 +265,9 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
     const int c0 = ct * kNT;
     const uint32_t j0 = (uint32_t)bgi * BG;
     const uint32_t W = p.W;
-
-    {
-        const size_t nw = lds_words<BG>(W);
-        float4* l4 = (float4*)lds;
-        for (size_t e = threadIdx.x; e < nw / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    __syncthreads();
+    const size_t nw = lds_words<BG>(W);
+    uint32_t* cnt = (uint32_t*)lds + nw;          // FIXED: per bucket row, K | N << 16
+    uint32_t* ctl = cnt + (size_t)BG * W;         // FIXED: [0] first max, [1] max, [2] max K
 
     const int k = lane >> 4;                 // row slot within a wave instruction
     const int q = lane & 15;                 // column pair within the tile
@@ -219,31 +292,62 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
     const uint32_t gstep = 4u * (uint32_t)p.lda * esz;
     const uint32_t tstep = (uint32_t)kTile * (uint32_t)p.lda * esz;
 
+    auto zero_lds = [&](bool with_counters) {
+        const size_t words = nw + (with_counters ? (size_t)BG * W + 4 : 0);
+        float4* l4 = (float4*)lds;
+        for (size_t e = threadIdx.x; e < nw / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (size_t e = nw + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
+    };
+
     auto load_tile = [&](PairRaw<AT> (&buf)[kGroups], int64_t tile) {
         const uint32_t vo = lane_vo + (uint32_t)tile * tstep;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) buf[g] = load_pair<VEC, AT>(rsrc, vo, (uint32_t)g * gstep, d1);
     };
 
+    auto tile_mag = [&](const PairRaw<AT> (&buf)[kGroups], uint32_t m) {
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) m = pair_mag(buf[g], m);
+        return m;
+    };
+
     // Lane (k, q) hashes row 4q + k of the tile and keeps, for instruction jj,
-    // the LDS byte offset and sign mask of local block (jj + k) mod BG.
-    auto hash_tile = [&](uint32_t (&hoff)[BG], uint32_t (&hsgn)[BG], int64_t tile) {
+    // the LDS byte offset and the sign word of local block (jj + k) mod BG.
+    // Float path: sign word = sign-bit mask.  Fixed path: the XOR word, and the
+    // row's contribution is counted per bucket row.
+    auto hash_tile = [&](uint32_t (&hoff)[BG], uint32_t (&hsgn)[BG], int64_t tile, bool fixed,
+                         uint32_t xneg) {
         const uint64_t grow = (uint64_t)(p.row_offset + r_begin + tile * kTile + 4 * q + k);
         uint4 w4a = row_words(grow, j0 >> 2, p.k0, p.k1);
         uint4 w4b = w4a;
         if (BG == 8 || (BG > 1 && ((j0 & 3u) + BG > 4u))) w4b = row_words(grow, (j0 >> 2) + 1u, p.k0, p.k1);
+        if (fixed) {
+#pragma unroll
+            for (int lb = 0; lb < BG; ++lb) {
+                const uint32_t wi = (j0 & 3u) + (uint32_t)lb;
+                const uint32_t w = (wi < 4u) ? word_of(w4a, wi) : word_of(w4b, wi - 4u);
+                __hip_atomic_fetch_add(&cnt[(uint32_t)lb * W + bucket_in_block(w, W)], 1u + ((w & 1u) << 16),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
 #pragma unroll
         for (int jj = 0; jj < BG; ++jj) {
             const uint32_t lb = (uint32_t)(jj + k) & (uint32_t)(BG - 1);
             const uint32_t wi = (j0 & 3u) + lb;            // word index from the first call
             const uint32_t w = (wi < 4u) ? word_of(w4a, wi) : word_of(w4b, wi - 4u);
-            hoff[jj] = lds_row<BG>(lb, bucket_in_block(w, W), W) * 4u;
-            hsgn[jj] = w << 31;
+            const uint32_t o = bucket_in_block(w, W);
+            if (fixed) {
+                hoff[jj] = lds_row_fixed<BG>(lb, o, W) * 4u;
+                hsgn[jj] = (w & 1u) ? xneg : kMagicBits;
+            } else {
+                hoff[jj] = lds_row<BG>(lb, o, W) * 4u;
+                hsgn[jj] = w << 31;
+            }
         }
     };
 
-    auto scatter_tile = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
-                            const uint32_t (&hsgn)[BG]) {
+    auto scatter_float = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                             const uint32_t (&hsgn)[BG]) {
         static_for<0, kGroups>([&](auto gc) {
             constexpr int g = decltype(gc)::value;
             float lo, hi;
@@ -261,29 +365,132 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
         });
     };
 
+    auto scatter_fixed = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                             const uint32_t (&hsgn)[BG], float scale, float magic) {
+        static_for<0, kGroups>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            float lo, hi;
+            to_f32(buf[g], lo, hi);
+            const uint32_t ylo = __float_as_uint(__builtin_fmaf(lo, scale, magic));
+            const uint32_t yhi = __float_as_uint(__builtin_fmaf(hi, scale, magic));
+#pragma unroll
+            for (int jj = 0; jj < BG; ++jj) {
+                const uint32_t off = bcast16<g>(hoff[jj]) + laneoff;
+                const uint32_t x = bcast16<g>(hsgn[jj]);
+                const uint64_t v = ((uint64_t)(yhi ^ x) << 32) | (uint64_t)(ylo ^ x);
+                unsigned long long* dst = (unsigned long long*)__builtin_assume_aligned((char*)lds + off, 8);
+                __hip_atomic_fetch_add(dst, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        });
+    };
+
     PairRaw<AT> bufA[kGroups], bufB[kGroups];
     uint32_t offA[BG], sgnA[BG], offB[BG], sgnB[BG];
-    int64_t tile = wave;
-    if (tile < ntiles) {
-        load_tile(bufA, tile);
-        hash_tile(offA, sgnA, tile);
-    }
-    // Software pipeline: the next tile's loads are in flight while the current
-    // tile is scattered; the loop is unrolled twice to ping-pong the buffers.
-    // Rows past the unit's end load as zero and add nothing.
-    while (tile < ntiles) {
-        int64_t nxt = tile + nwaves;
-        if (nxt < ntiles) load_tile(bufB, nxt);
-        scatter_tile(bufA, offA, sgnA);
-        if (nxt >= ntiles) break;
-        hash_tile(offB, sgnB, nxt);
-        tile = nxt;
-        nxt = tile + nwaves;
-        if (nxt < ntiles) load_tile(bufA, nxt);
-        scatter_tile(bufB, offB, sgnB);
-        if (nxt >= ntiles) break;
-        hash_tile(offA, sgnA, nxt);
-        tile = nxt;
+
+    // Stream the unit once; `fixed` selects the accumulation.  bufA holds the
+    // wave's first tile on entry when `preloaded`.  Returns the lane's largest
+    // input magnitude bits.
+    auto run = [&](bool fixed, bool preloaded, const FixedParams& fp) {
+        uint32_t mag = 0;
+        int64_t tile = wave;
+        if (tile < ntiles) {
+            if (!preloaded) load_tile(bufA, tile);
+            hash_tile(offA, sgnA, tile, fixed, fp.xneg);
+        }
+        // Software pipeline: the next tile's loads are in flight while the
+        // current tile is scattered; unrolled twice to ping-pong the buffers.
+        // Rows past the unit's end load as zero and add nothing.
+        while (tile < ntiles) {
+            int64_t nxt = tile + nwaves;
+            if (nxt < ntiles) load_tile(bufB, nxt);
+            if (fixed) {
+                mag = tile_mag(bufA, mag);
+                scatter_fixed(bufA, offA, sgnA, fp.scale, fp.magic);
+            } else {
+                scatter_float(bufA, offA, sgnA);
+            }
+            if (nxt >= ntiles) break;
+            hash_tile(offB, sgnB, nxt, fixed, fp.xneg);
+            tile = nxt;
+            nxt = tile + nwaves;
+            if (nxt < ntiles) load_tile(bufA, nxt);
+            if (fixed) {
+                mag = tile_mag(bufB, mag);
+                scatter_fixed(bufB, offB, sgnB, fp.scale, fp.magic);
+            } else {
+                scatter_float(bufB, offB, sgnB);
+            }
+            if (nxt >= ntiles) break;
+            hash_tile(offA, sgnA, nxt, fixed, fp.xneg);
+            tile = nxt;
+        }
+        return mag;
+    };
+
+    auto wave_max = [&](uint32_t v) {
+        for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+        return v;
+    };
+    auto to_f32bits = [&](uint32_t m) -> uint32_t {
+        if constexpr (sizeof(AT) == 4) return m;
+        else return mag16_to_f32bits(m, std::is_same<AT, __hip_bfloat16>::value);
+    };
+
+    bool fixed_ok = false;
+    FixedParams fp = fixed_params(0, 0);
+    if constexpr (FIXED) {
+        zero_lds(true);
+        __syncthreads();
+        // Scale from the first tile of every wave, with one binade of headroom.
+        uint32_t m0 = 0;
+        if (wave < ntiles) {
+            load_tile(bufA, wave);
+            m0 = to_f32bits(tile_mag(bufA, 0u));
+        }
+        m0 = wave_max(m0);
+        if (lane == 0) atomicMax(&ctl[0], m0);
+        __syncthreads();
+        const uint32_t first = ctl[0];
+        if (first < 0x7F800000u) {
+            int E = binade_of(first) + 1;
+            int c = 0;
+            for (int attempt = 0; attempt < 2 && !fixed_ok; ++attempt) {
+                if (attempt > 0) {
+                    zero_lds(true);
+                    __syncthreads();
+                }
+                fp = fixed_params(E, c);
+                uint32_t m = to_f32bits(run(true, attempt == 0, fp));
+                m = wave_max(m);
+                if (lane == 0) atomicMax(&ctl[1], m);
+                __syncthreads();
+                uint32_t kmax = 0;
+                for (uint32_t e = threadIdx.x; e < (uint32_t)BG * W; e += blockDim.x) kmax = max(kmax, cnt[e] & 0xFFFFu);
+                kmax = wave_max(kmax);
+                if (lane == 0) atomicMax(&ctl[2], kmax);
+                __syncthreads();
+                const uint32_t mall = ctl[1], kall = ctl[2];
+                if (mall >= 0x7F800000u) break;                    // non-finite input
+                const bool mag_ok = binade_of(mall) <= E;          // |x| < 2^(E+1)
+                const bool cnt_ok = kall < (1u << (10 + c));
+                fixed_ok = mag_ok && cnt_ok;
+                if (!fixed_ok) {
+                    E = max(E, binade_of(mall));
+                    while (kall >= (1u << (10 + c))) ++c;
+                }
+                __syncthreads();
+                if (!fixed_ok && threadIdx.x == 0) { ctl[1] = 0; ctl[2] = 0; }
+            }
+        }
+        if (!fixed_ok) {
+            zero_lds(false);
+            __syncthreads();
+            run(false, false, fp);
+        }
+    } else {
+        zero_lds(false);
+        __syncthreads();
+        run(false, false, fp);
     }
     __syncthreads();
 
@@ -309,18 +516,29 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
             const uint32_t cp = e % (kNT / 2), o = (e / (kNT / 2)) % W, lb = e / ((kNT / 2) * W);
             const int cc = c0 + 2 * (int)cp;
             if (cc >= p.n) continue;
-            const uint32_t li = lds_row<BG>(lb, o, W) + 2 * cp;
             const int64_t b = (int64_t)(j0 + lb) * W + o;
+            float v0, v1;
+            if (fixed_ok) {
+                // exact sums of the unit, rounded once to FP32
+                const uint32_t* wrd = (const uint32_t*)lds + lds_row_fixed<BG>(lb, o, W) + 2 * cp;
+                const uint32_t cv = cnt[lb * W + o];
+                const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)fp.B - (int64_t)(cv >> 16);
+                v0 = ldexpf((float)((int64_t)wrd[0] - kb), -fp.S);
+                v1 = ldexpf((float)((int64_t)wrd[1] - kb), -fp.S);
+            } else {
+                const uint32_t li = lds_row<BG>(lb, o, W) + 2 * cp;
+                v0 = lds[li];
+                v1 = lds[li + 1];
+            }
             const uint64_t site = (uint64_t)r0g * dn + (uint64_t)b * (uint64_t)p.n + (uint64_t)cc;
             uint32_t u0 = 0, u1 = 0;
             if (p.mode >= 2) {
                 u0 = round_bits(site, p.epoch, p.k0, p.k1);
                 u1 = round_bits(site + 1, p.epoch, p.k0, p.k1);
             }
-            const uint16_t h0 = quantize(p.mode, lds[li] * p.scale, u0);
+            const uint16_t h0 = quantize(p.mode, v0 * p.scale, u0);
             // -0.0 leaves the neighbouring half unchanged (x + -0 == x for every x)
-            const uint16_t h1 = (cc + 1 < p.n) ? quantize(p.mode, lds[li + 1] * p.scale, u1)
-                                               : (uint16_t)0x8000u;
+            const uint16_t h1 = (cc + 1 < p.n) ? quantize(p.mode, v1 * p.scale, u1) : (uint16_t)0x8000u;
             const uint32_t packed = (uint32_t)h0 | ((uint32_t)h1 << 16);
             h2 hv = __builtin_bit_cast(h2, packed);
             __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * p.ldsa + cc), hv);
@@ -384,11 +602,11 @@ __global__ void quantize_kernel(int mode, const float* x, uint16_t* out, int64_t
     }
 }
 
-template <typename AT, int BG, bool VEC>
-hipError_t launch_typed(const Plan& plan, const ApplyArgs& a, hipStream_t st)
+template <typename AT, int BG, bool VEC, bool FIXED>
+hipError_t launch_kernel(const Plan& plan, const ApplyArgs& a, hipStream_t st)
 {
     static size_t attr_bytes = 0;
-    auto kern = apply_kernel<AT, BG, VEC>;
+    auto kern = apply_kernel<AT, BG, VEC, FIXED>;
     if (plan.lds_bytes > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)plan.lds_bytes);
@@ -398,6 +616,12 @@ hipError_t launch_typed(const Plan& plan, const ApplyArgs& a, hipStream_t st)
     const int64_t grid = plan.units * (int64_t)plan.col_tiles * plan.bgroups;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)(64 * plan.waves)), plan.lds_bytes, st, a);
     return hipGetLastError();
+}
+
+template <typename AT, int BG, bool VEC>
+hipError_t launch_typed(const Plan& plan, const ApplyArgs& a, hipStream_t st)
+{
+    return a.mode == 0 ? launch_kernel<AT, BG, VEC, false>(plan, a, st) : launch_kernel<AT, BG, VEC, true>(plan, a, st);
 }
 
 template <typename AT, bool VEC>
@@ -435,11 +659,13 @@ int apply_max_waves(int32_t a_dtype)
 
 size_t apply_lds_bytes(int32_t bg, int64_t W)
 {
+    // partial + per-bucket-row counters + 4 control words
+    const size_t extra = ((size_t)bg * (size_t)W + 4) * 4;
     switch (bg) {
-    case 1: return lds_words<1>((uint32_t)W) * 4;
-    case 2: return lds_words<2>((uint32_t)W) * 4;
-    case 4: return lds_words<4>((uint32_t)W) * 4;
-    case 8: return lds_words<8>((uint32_t)W) * 4;
+    case 1: return lds_words<1>((uint32_t)W) * 4 + extra;
+    case 2: return lds_words<2>((uint32_t)W) * 4 + extra;
+    case 4: return lds_words<4>((uint32_t)W) * 4 + extra;
+    case 8: return lds_words<8>((uint32_t)W) * 4 + extra;
     default: return (size_t)-1;
     }
 }
