@@ -37,7 +37,9 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--modes", default="f32,sr,dither", help="extra accumulation modes to time")
+    p.add_argument("--modes", default="f32,sr,dither,a32",
+                   help="extra runs to time: f32/sr/dither accumulation on the FP16 input, a32 = FP32-stored "
+                        "input with FP32 accumulation; empty = the headline run only")
     return p.parse_args()
 
 
@@ -140,18 +142,20 @@ def main():
 
     modes = {}
     mode_codes = {"f32": ACC_F32, "sr": ACC_F16_SR, "dither": ACC_F16_DITHER}
-    for name in [m for m in args.modes.split(",") if m]:
+    extra = [m for m in args.modes.split(",") if m]
+    for name in [m for m in extra if m in mode_codes]:
         code = mode_codes[name]
         steps = max(20, args.steps // 4)
         _, kms, _, _ = measure(code, steps, 5, A)
         out_bytes = D * N * (4 if code == ACC_F32 else 2)
         modes[name] = {"kernel_ms": round(kms, 4), "GB/s": round((M * N * 2 + out_bytes) / (kms * 1e-3) / 1e9, 1)}
-    # FP32-stored A with FP32 accumulation (the plain path)
-    A32 = A.float()
-    _, k32, _, _ = measure(ACC_F32, max(20, args.steps // 4), 5, A32)
-    modes["a_f32_acc_f32"] = {"kernel_ms": round(k32, 4),
-                              "GB/s": round((M * N * 4 + D * N * 4) / (k32 * 1e-3) / 1e9, 1)}
-    del A32
+    if "a32" in extra:
+        # FP32-stored A with FP32 accumulation (the plain path)
+        A32 = A.float()
+        _, k32, _, _ = measure(ACC_F32, max(20, args.steps // 4), 5, A32)
+        modes["a_f32_acc_f32"] = {"kernel_ms": round(k32, 4),
+                                  "GB/s": round((M * N * 4 + D * N * 4) / (k32 * 1e-3) / 1e9, 1)}
+        del A32
 
     traffic = measured_traffic()
     line = {

@@ -66,17 +66,18 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
 {
     const int64_t W = h->d / h->s;
     const sk_schedule* f = h->forced ? &h->sched : nullptr;
+    const bool dual = h->rounding == SK_ACC_F32;   // FP32 mode keeps two fields per element
     Plan pl;
     // blocks per workgroup
     if (f && f->block_group) {
         pl.bg = f->block_group;
         if (h->s % pl.bg) return set_error(SK_EINVAL, "block_group %d does not divide s = %d", pl.bg, h->s);
-        if (apply_lds_bytes(pl.bg, W) > dev.lds_max)
+        if (apply_lds_bytes(pl.bg, W, dual) > dev.lds_max)
             return set_error(SK_EUNSUPPORTED, "block_group %d needs %zu B of LDS (device has %zu)", pl.bg,
-                             apply_lds_bytes(pl.bg, W), dev.lds_max);
+                             apply_lds_bytes(pl.bg, W, dual), dev.lds_max);
     } else {
         for (int bg : {8, 4, 2, 1}) {
-            if (h->s % bg == 0 && apply_lds_bytes(bg, W) <= dev.lds_max) {
+            if (h->s % bg == 0 && apply_lds_bytes(bg, W, dual) <= dev.lds_max) {
                 pl.bg = bg;
                 break;
             }
@@ -85,11 +86,13 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
             return set_error(SK_EUNSUPPORTED, "d/s = %lld bucket rows of 32 FP32 values exceed the %zu B of LDS",
                              (long long)W, dev.lds_max);
     }
-    pl.lds_bytes = apply_lds_bytes(pl.bg, W);
+    pl.lds_bytes = apply_lds_bytes(pl.bg, W, dual);
     pl.bgroups = h->s / pl.bg;
     pl.col_tiles = (int32_t)((n + 31) / 32);
     const int maxw = apply_max_waves(a_dtype);
-    pl.waves = (f && f->waves) ? f->waves : maxw;
+    // 8 waves measured fastest for up to 4 blocks per workgroup, 16 for 8 blocks
+    const int autow = std::min(maxw, pl.bg >= 8 ? 16 : 8);
+    pl.waves = (f && f->waves) ? f->waves : autow;
     if (pl.waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", pl.waves, maxw);
     const int64_t per_unit = (int64_t)pl.col_tiles * pl.bgroups;
     const int esz = elem_size(a_dtype);

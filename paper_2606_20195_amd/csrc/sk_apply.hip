@@ -203,6 +203,16 @@ __device__ __forceinline__ uint32_t pair_mag(const PairRaw<AT>& r, uint32_t m)
     const u16x2 b = __builtin_bit_cast(u16x2, m);
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(a, b));
 }
+template <>
+__device__ __forceinline__ uint32_t pair_mag<__half>(const PairRaw<__half>& r, uint32_t m)
+{
+    // FP16: m = maximum3(m, x, -x) per half, one instruction; the IEEE maximum
+    // propagates NaN, so non-finite input still shows up as >= 0x7C00.
+    uint32_t out;
+    asm volatile("v_pk_maximum3_f16 %0, %1, %2, %2 neg_lo:[0,0,1] neg_hi:[0,0,1]"
+                 : "=v"(out) : "v"(m), "v"(r.v));
+    return out;
+}
 __device__ __forceinline__ uint32_t mag16_to_f32bits(uint32_t m, bool bf16)
 {
     const uint32_t a = max(m & 0xFFFFu, m >> 16);
@@ -238,7 +248,11 @@ __device__ __forceinline__ int binade_of(uint32_t magbits)
     return e < -126 ? -126 : e;
 }
 
-template <typename AT, int BG, bool VEC, bool FIXED>
+// ACC: 0 = FP32 LDS atomics, 1 = one fixed-point field per element (FP16
+// modes), 2 = two fields per element (FP32 mode): the rounded value and its
+// residual at 2^-21 finer resolution, kept in two LDS arrays with the same
+// layout, so each unit is summed with about 41 significant bits.
+template <typename AT, int BG, bool VEC, int ACC>
 __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
 {
     extern __shared__ float lds[];
@@ -266,8 +280,10 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
     const uint32_t j0 = (uint32_t)bgi * BG;
     const uint32_t W = p.W;
     const size_t nw = lds_words<BG>(W);
-    uint32_t* cnt = (uint32_t*)lds + nw;          // FIXED: per bucket row, K | N << 16
-    uint32_t* ctl = cnt + (size_t)BG * W;         // FIXED: [0] first max, [1] max, [2] max K
+    const size_t narr = (ACC == 2) ? 2 : 1;       // fixed-point arrays
+    uint32_t* cnt = (uint32_t*)lds + narr * nw;   // per bucket row, K | N << 16
+    uint32_t* ctl = cnt + (size_t)BG * W;         // [0] first max, [1] max, [2] max K
+    const uint32_t lo_off = (uint32_t)(nw * 4);   // byte offset of the residual array
 
     const int k = lane >> 4;                 // row slot within a wave instruction
     const int q = lane & 15;                 // column pair within the tile
@@ -293,10 +309,11 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
     const uint32_t tstep = (uint32_t)kTile * (uint32_t)p.lda * esz;
 
     auto zero_lds = [&](bool with_counters) {
-        const size_t words = nw + (with_counters ? (size_t)BG * W + 4 : 0);
+        const size_t base = with_counters ? narr * nw : nw;
+        const size_t words = base + (with_counters ? (size_t)BG * W + 4 : 0);
         float4* l4 = (float4*)lds;
-        for (size_t e = threadIdx.x; e < nw / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (size_t e = nw + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
+        for (size_t e = threadIdx.x; e < base / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (size_t e = base + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
     };
 
     auto load_tile = [&](PairRaw<AT> (&buf)[kGroups], int64_t tile) {
@@ -384,13 +401,44 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
         });
     };
 
+    // Two fields per element: y = x*2^S + (2^23 + B) rounds x*2^S to an integer
+    // Q = y - 2^23 - B, the FMA x*2^S - Q is the exact residual (|r| <= 1/2),
+    // and z = r*2^21 + (2^23 + B) is its fixed-point form.
+    auto scatter_dual = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                            const uint32_t (&hsgn)[BG], float scale, float magic) {
+        static_for<0, kGroups>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            float lo, hi;
+            to_f32(buf[g], lo, hi);
+            const float ylo = __builtin_fmaf(lo, scale, magic);
+            const float yhi = __builtin_fmaf(hi, scale, magic);
+            const float rlo = __builtin_fmaf(lo, scale, -(ylo - magic));
+            const float rhi = __builtin_fmaf(hi, scale, -(yhi - magic));
+            const uint32_t zlo = __float_as_uint(__builtin_fmaf(rlo, 2097152.0f, magic));
+            const uint32_t zhi = __float_as_uint(__builtin_fmaf(rhi, 2097152.0f, magic));
+            const uint32_t alo = __float_as_uint(ylo), ahi = __float_as_uint(yhi);
+#pragma unroll
+            for (int jj = 0; jj < BG; ++jj) {
+                const uint32_t off = bcast16<g>(hoff[jj]) + laneoff;
+                const uint32_t x = bcast16<g>(hsgn[jj]);
+                const uint64_t v = ((uint64_t)(ahi ^ x) << 32) | (uint64_t)(alo ^ x);
+                const uint64_t w = ((uint64_t)(zhi ^ x) << 32) | (uint64_t)(zlo ^ x);
+                unsigned long long* dst = (unsigned long long*)__builtin_assume_aligned((char*)lds + off, 8);
+                unsigned long long* dst2 = (unsigned long long*)__builtin_assume_aligned((char*)lds + off + lo_off, 8);
+                __hip_atomic_fetch_add(dst, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(dst2, (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        });
+    };
+
     PairRaw<AT> bufA[kGroups], bufB[kGroups];
     uint32_t offA[BG], sgnA[BG], offB[BG], sgnB[BG];
 
     // Stream the unit once; `fixed` selects the accumulation.  bufA holds the
     // wave's first tile on entry when `preloaded`.  Returns the lane's largest
     // input magnitude bits.
-    auto run = [&](bool fixed, bool preloaded, const FixedParams& fp) {
+    auto run = [&](int acc, bool preloaded, const FixedParams& fp) {
+        const bool fixed = acc != 0;
         uint32_t mag = 0;
         int64_t tile = wave;
         if (tile < ntiles) {
@@ -403,9 +451,16 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
         while (tile < ntiles) {
             int64_t nxt = tile + nwaves;
             if (nxt < ntiles) load_tile(bufB, nxt);
-            if (fixed) {
-                mag = tile_mag(bufA, mag);
-                scatter_fixed(bufA, offA, sgnA, fp.scale, fp.magic);
+            if (acc == 2) {
+                if constexpr (ACC == 2) {
+                    mag = tile_mag(bufA, mag);
+                    scatter_dual(bufA, offA, sgnA, fp.scale, fp.magic);
+                }
+            } else if (acc == 1) {
+                if constexpr (ACC == 1) {
+                    mag = tile_mag(bufA, mag);
+                    scatter_fixed(bufA, offA, sgnA, fp.scale, fp.magic);
+                }
             } else {
                 scatter_float(bufA, offA, sgnA);
             }
@@ -414,9 +469,16 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
             tile = nxt;
             nxt = tile + nwaves;
             if (nxt < ntiles) load_tile(bufA, nxt);
-            if (fixed) {
-                mag = tile_mag(bufB, mag);
-                scatter_fixed(bufB, offB, sgnB, fp.scale, fp.magic);
+            if (acc == 2) {
+                if constexpr (ACC == 2) {
+                    mag = tile_mag(bufB, mag);
+                    scatter_dual(bufB, offB, sgnB, fp.scale, fp.magic);
+                }
+            } else if (acc == 1) {
+                if constexpr (ACC == 1) {
+                    mag = tile_mag(bufB, mag);
+                    scatter_fixed(bufB, offB, sgnB, fp.scale, fp.magic);
+                }
             } else {
                 scatter_float(bufB, offB, sgnB);
             }
@@ -438,7 +500,7 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
 
     bool fixed_ok = false;
     FixedParams fp = fixed_params(0, 0);
-    if constexpr (FIXED) {
+    if constexpr (ACC != 0) {
         zero_lds(true);
         __syncthreads();
         // Scale from the first tile of every wave, with one binade of headroom.
@@ -460,7 +522,7 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
                     __syncthreads();
                 }
                 fp = fixed_params(E, c);
-                uint32_t m = to_f32bits(run(true, attempt == 0, fp));
+                uint32_t m = to_f32bits(run(ACC, attempt == 0, fp));
                 m = wave_max(m);
                 if (lane == 0) atomicMax(&ctl[1], m);
                 __syncthreads();
@@ -485,12 +547,12 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
         if (!fixed_ok) {
             zero_lds(false);
             __syncthreads();
-            run(false, false, fp);
+            run(0, false, fp);
         }
     } else {
         zero_lds(false);
         __syncthreads();
-        run(false, false, fp);
+        run(0, false, fp);
     }
     __syncthreads();
 
@@ -503,9 +565,20 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
             const uint32_t c = e % kNT, o = (e / kNT) % W, lb = e / (kNT * W);
             const int cc = c0 + (int)c;
             if (cc >= p.n) continue;
-            const float v = lds[lds_row<BG>(lb, o, W) + c] * p.scale;
+            float v;
+            if (ACC == 2 && fixed_ok) {
+                // exact unit sum sum(q_hi) * 2^21 + sum(q_lo), rounded once to FP32
+                const uint32_t wi = lds_row_fixed<BG>(lb, o, W) + c;
+                const uint32_t cv = cnt[lb * W + o];
+                const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)fp.B - (int64_t)(cv >> 16);
+                const int64_t hi = (int64_t)((const uint32_t*)lds)[wi] - kb;
+                const int64_t lo = (int64_t)((const uint32_t*)lds)[nw + wi] - kb;
+                v = (float)ldexp((double)(hi * 2097152 + lo), -(fp.S + 21));
+            } else {
+                v = lds[lds_row<BG>(lb, o, W) + c];
+            }
             const int64_t b = (int64_t)(j0 + lb) * W + o;
-            unsafeAtomicAdd(SA + b * p.ldsa + cc, v);
+            unsafeAtomicAdd(SA + b * p.ldsa + cc, v * p.scale);
         }
     } else {
         typedef _Float16 h2 __attribute__((ext_vector_type(2)));
@@ -602,11 +675,11 @@ __global__ void quantize_kernel(int mode, const float* x, uint16_t* out, int64_t
     }
 }
 
-template <typename AT, int BG, bool VEC, bool FIXED>
+template <typename AT, int BG, bool VEC, int ACC>
 hipError_t launch_kernel(const Plan& plan, const ApplyArgs& a, hipStream_t st)
 {
     static size_t attr_bytes = 0;
-    auto kern = apply_kernel<AT, BG, VEC, FIXED>;
+    auto kern = apply_kernel<AT, BG, VEC, ACC>;
     if (plan.lds_bytes > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)plan.lds_bytes);
@@ -621,7 +694,7 @@ hipError_t launch_kernel(const Plan& plan, const ApplyArgs& a, hipStream_t st)
 template <typename AT, int BG, bool VEC>
 hipError_t launch_typed(const Plan& plan, const ApplyArgs& a, hipStream_t st)
 {
-    return a.mode == 0 ? launch_kernel<AT, BG, VEC, false>(plan, a, st) : launch_kernel<AT, BG, VEC, true>(plan, a, st);
+    return a.mode == 0 ? launch_kernel<AT, BG, VEC, 2>(plan, a, st) : launch_kernel<AT, BG, VEC, 1>(plan, a, st);
 }
 
 template <typename AT, bool VEC>
@@ -657,15 +730,16 @@ int apply_max_waves(int32_t a_dtype)
     return (a_dtype == SK_F32 ? kMaxThreads<float> : kMaxThreads<__half>) / 64;
 }
 
-size_t apply_lds_bytes(int32_t bg, int64_t W)
+size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual)
 {
-    // partial + per-bucket-row counters + 4 control words
+    // fixed-point array(s) + per-bucket-row counters + 4 control words
     const size_t extra = ((size_t)bg * (size_t)W + 4) * 4;
+    const size_t narr = dual ? 2 : 1;
     switch (bg) {
-    case 1: return lds_words<1>((uint32_t)W) * 4 + extra;
-    case 2: return lds_words<2>((uint32_t)W) * 4 + extra;
-    case 4: return lds_words<4>((uint32_t)W) * 4 + extra;
-    case 8: return lds_words<8>((uint32_t)W) * 4 + extra;
+    case 1: return narr * lds_words<1>((uint32_t)W) * 4 + extra;
+    case 2: return narr * lds_words<2>((uint32_t)W) * 4 + extra;
+    case 4: return narr * lds_words<4>((uint32_t)W) * 4 + extra;
+    case 8: return narr * lds_words<8>((uint32_t)W) * 4 + extra;
     default: return (size_t)-1;
     }
 }

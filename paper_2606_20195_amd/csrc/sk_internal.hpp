@@ -42,7 +42,7 @@ struct Plan {
     size_t lds_bytes = 0;
 };
 
-size_t apply_lds_bytes(int32_t bg, int64_t W);
+size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual);
 int make_plan(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo &dev,
               Plan *out);
 int apply_max_waves(int32_t a_dtype);
