@@ -41,6 +41,7 @@ extern "C" {
 #define SK_EUNSUPPORTED -2   /* valid but not supported (alignment, size)     */
 #define SK_ENOMEM       -3   /* device allocation failed                      */
 #define SK_EHIP         -4   /* a HIP runtime call failed                     */
+#define SK_ENOTCONV     -5   /* sketch_solve: stopping test not reached       */
 
 /* ---- element types ----------------------------------------------------- */
 #define SK_F32  0
@@ -152,6 +153,95 @@ int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t *buckets,
  */
 int sketch_quantize(int32_t mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
                     uint32_t epoch, uint64_t site0, void *stream);
+
+/* ---- least squares -------------------------------------------------------- */
+
+/*
+ * Options of sketch_solve.  Zero fields take the defaults in brackets.
+ *   tol         stopping tolerance on the normal-equations residual
+ *               ||A^T r|| / (||A||_F ||r||), r = b - A x, evaluated in FP64;
+ *               the solve also stops when ||r|| <= tol ||b||        [1e-10]
+ *   inner_tol   LSQR tolerance (Paige-Saunders tests on the corrected
+ *               problem, relative to ||r||)                          [1e-6]
+ *   max_refine  FP64 refinement steps                                [10]
+ *   max_inner   LSQR iterations per refinement step                  [100]
+ *   round_epoch rounding-noise stream of the SR / dither sketch of A  [0]
+ */
+typedef struct sk_solve_opts {
+    double tol;
+    double inner_tol;
+    int32_t max_refine;
+    int32_t max_inner;
+    uint32_t round_epoch;
+    int32_t reserved[3];  /* must be zero */
+} sk_solve_opts;
+
+/* Statistics of one sketch_solve call (times from HIP events, in ms). */
+typedef struct sk_solve_info {
+    int32_t converged;       /* 1 if the stopping test was met                */
+    int32_t refine_steps;    /* FP64 residual evaluations after the start     */
+    int32_t inner_iters;     /* LSQR iterations over all steps                */
+    int32_t reserved0;
+    double crit;             /* ||A^T r|| / (||A||_F ||r||) of the returned x */
+    double rel_residual;     /* ||b - A x|| / ||b|| of the returned x         */
+    double rel_residual_x0;  /* the same for the sketch-and-solve start x0    */
+    double ms_sketch;        /* sketch of A and b                             */
+    double ms_factor;        /* Gram matrix, Cholesky, R^-1, x0               */
+    double ms_refine;        /* residuals and LSQR                            */
+    double ms_total;
+    double reserved[4];
+} sk_solve_info;
+
+/*
+ * sketch_solve -- least squares min ||A x - b||_2 for A (m x n, m = the
+ * handle's m) by sketch-and-precondition with FP64 iterative refinement.
+ * The paper forms SA and Sb and solves the sketched problem with an FP32
+ * reduced QR and a triangular solve (Section 5.1, sketch-and-solve); it names
+ * sketch-and-precondition as related and future work (Section 3.1; Section 6).
+ * Here: SA = S A with the handle's accumulation mode (Section 4) and Sb in
+ * FP32; R from an FP32 Householder QR of SA; P = R^-1 formed explicitly in
+ * FP32; x0 = P (Q^T Sb) (the sketch-and-solve solution); then repeat:
+ * r = b - A x in FP64 (A upcast exactly); stop when the criterion of
+ * sk_solve_opts holds; LSQR (Paige & Saunders 1982) on min ||A P y - r/||r|| ||
+ * with the products by A in FP32 over A in its storage type; x += ||r|| P y in
+ * FP64.
+ *   A      device, m x n, element type a_dtype (SK_F32/F16/BF16), lda >= n.
+ *   n      1 .. 1024 and n <= d; d <= 16384.
+ *   b      device FP64, m values.      x  device FP64, n values (output).
+ *   opts   NULL for the defaults.      info  may be NULL.
+ * Synchronises `stream` a few times per refinement step to read the stopping
+ * tests.  Device workspace is allocated by the handle on first use (and when
+ * a larger problem arrives) and kept until sketch_destroy.
+ * Errors: SK_EINVAL (arguments; SA numerically rank deficient), SK_EUNSUPPORTED,
+ * SK_ENOMEM, SK_EHIP, SK_ENOTCONV (x holds the last iterate and info its
+ * criterion).
+ */
+int sketch_solve(sk_handle h, const void *A, int32_t a_dtype, int64_t n, int64_t lda, const double *b,
+                 double *x, const sk_solve_opts *opts, sk_solve_info *info, void *stream);
+
+/*
+ * sketch_qr_f32 -- in-place FP32 Householder QR of the first k columns of M
+ * (rows x cols, row-major, leading dimension ldm, k <= min(rows, cols)), the
+ * factorisation sketch_solve applies to [SA | Sb].  The reflectors
+ * H_j = I - tau_j v_j v_j^T (v_j[j] = 1, LAPACK convention) are applied to all
+ * `cols` columns.  On return the upper triangle of M[0:k, 0:cols] holds R (and
+ * Q^T applied to the columns beyond k), v_j below the diagonal and tau_j in
+ * tau[j] (device, k floats).  rows <= 16384, cols <= 1025.  A testing export.
+ * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_EHIP.
+ */
+int sketch_qr_f32(float *M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float *tau, void *stream);
+
+/*
+ * sketch_trinv_f32 -- P = R^-1 for the upper-triangular R in the first n rows
+ * and columns of R (leading dimension ldr), by FP32 back substitution, one
+ * column of P at a time.  P and PT (= P^T) are n x n with leading dimension
+ * ldp; entries below (above) the diagonal are zero.  *bad (device int32) is
+ * set to 1 if a diagonal entry of R is zero or a result is not finite (it is
+ * not cleared).  n <= 1024.  A testing export of the preconditioner sketch_solve
+ * uses.  Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_trinv_f32(const float *R, int64_t n, int64_t ldr, float *P, float *PT, int64_t ldp, int32_t *bad,
+                     void *stream);
 
 /* sketch_last_error -- message of the last failure on this thread ("" if none). */
 const char *sketch_last_error(void);

@@ -12,10 +12,11 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, F16, F32,
-                   Schedule, SketchError, check, load)
+from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, ENOTCONV, F16, F32,
+                   Schedule, SketchError, SolveInfo, SolveOpts, check, load)
 
-__all__ = ["Sketch", "SketchError", "Schedule", "quantize", "version", "ACC_F32", "ACC_F16_RN",
+__all__ = ["Sketch", "SketchError", "Schedule", "quantize", "qr_f32", "trinv_f32", "version", "ACC_F32",
+           "ACC_F16_RN",
            "ACC_F16_SR", "ACC_F16_DITHER", "F32", "F16", "BF16", "ACCUMULATE"]
 
 
@@ -100,6 +101,34 @@ class Sketch:
                                      _stream(stream)), "sketch_apply")
         return SA
 
+    def solve(self, A, b, x=None, tol=0.0, inner_tol=0.0, max_refine=0, max_inner=0, epoch=0, stream=None,
+              raise_on_notconv=True):
+        """x = argmin ||A x - b|| (FP64) for A (m x n, this sketch's m) on the device.
+
+        b: FP64 device vector of m values.  Returns (x, info dict).  Zero
+        options take the library defaults (tol 1e-10, inner_tol 1e-6,
+        max_refine 10, max_inner 100).
+        """
+        torch = _torch()
+        lda = _matrix(A, "A")
+        m, n = A.shape
+        if m != self.m:
+            raise ValueError("A has %d rows, the sketch has m = %d" % (m, self.m))
+        if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m or not b.is_cuda:
+            raise ValueError("b must be a contiguous FP64 device vector of %d values" % m)
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=A.device)
+        if x.dtype != torch.float64 or not x.is_contiguous() or x.numel() != n:
+            raise ValueError("x must be a contiguous FP64 vector of %d values" % n)
+        opts = SolveOpts(float(tol), float(inner_tol), int(max_refine), int(max_inner), int(epoch) & 0xFFFFFFFF)
+        info = SolveInfo()
+        rc = self._lib.sketch_solve(self._h, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), n, lda,
+                                    ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.byref(opts), ctypes.byref(info), _stream(stream))
+        if rc != ENOTCONV or raise_on_notconv:
+            check(rc, "sketch_solve")
+        return x, info.as_dict()
+
     def set_schedule(self, chunk_rows=0, block_group=0, waves=0, xcd_remap=1):
         sch = Schedule(chunk_rows, block_group, waves, xcd_remap)
         check(self._lib.sketch_set_schedule(self._h, ctypes.byref(sch)), "sketch_set_schedule")
@@ -120,6 +149,35 @@ class Sketch:
         check(self._lib.sketch_hash(self._h, int(row_begin), int(count), ctypes.c_void_p(b.data_ptr()),
                                     ctypes.c_void_p(g.data_ptr()), _stream(stream)), "sketch_hash")
         return b, g
+
+
+def qr_f32(M, k, stream=None):
+    """In-place FP32 Householder QR of the first k columns of M (device FP32,
+    unit column stride); returns tau (k floats)."""
+    torch = _torch()
+    ldm = _matrix(M, "M")
+    if M.dtype != torch.float32:
+        raise ValueError("M must be FP32")
+    tau = torch.empty(max(int(k), 1), dtype=torch.float32, device=M.device)
+    check(load().sketch_qr_f32(ctypes.c_void_p(M.data_ptr()), M.shape[0], M.shape[1], ldm, int(k),
+                               ctypes.c_void_p(tau.data_ptr()), _stream(stream)), "sketch_qr_f32")
+    return tau[:k]
+
+
+def trinv_f32(R, stream=None):
+    """(P, P^T, bad) with P = R^-1 for the upper triangle of a square FP32 device matrix R."""
+    torch = _torch()
+    ldr = _matrix(R, "R")
+    n = R.shape[0]
+    if R.dtype != torch.float32 or R.shape[1] < n:
+        raise ValueError("R must be FP32 with at least n columns")
+    P = torch.empty((n, n), dtype=torch.float32, device=R.device)
+    PT = torch.empty((n, n), dtype=torch.float32, device=R.device)
+    bad = torch.zeros(1, dtype=torch.int32, device=R.device)
+    check(load().sketch_trinv_f32(ctypes.c_void_p(R.data_ptr()), n, ldr, ctypes.c_void_p(P.data_ptr()),
+                                  ctypes.c_void_p(PT.data_ptr()), n, ctypes.c_void_p(bad.data_ptr()),
+                                  _stream(stream)), "sketch_trinv_f32")
+    return P, PT, bad
 
 
 def quantize(mode, x, seed=0, epoch=0, site0=0, stream=None):

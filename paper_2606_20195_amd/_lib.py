@@ -14,13 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsketch.so")
 
 # return codes (include/sketch.h)
-OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOTCONV = 0, -1, -2, -3, -4, -5
 F32, F16, BF16 = 0, 1, 2
 ACC_F32, ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER = 0, 1, 2, 3
 ACCUMULATE = 1
 
 EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedule", "sketch_plan",
-           "sketch_hash", "sketch_quantize", "sketch_last_error", "sketch_version")
+           "sketch_hash", "sketch_quantize", "sketch_solve", "sketch_qr_f32", "sketch_trinv_f32",
+           "sketch_last_error", "sketch_version")
 
 
 class Schedule(ctypes.Structure):
@@ -31,6 +32,22 @@ class Schedule(ctypes.Structure):
     def as_dict(self):
         return dict(chunk_rows=self.chunk_rows, block_group=self.block_group, waves=self.waves,
                     xcd_remap=self.xcd_remap)
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("max_inner", ctypes.c_int32), ("round_epoch", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("crit", ctypes.c_double), ("rel_residual", ctypes.c_double),
+                ("rel_residual_x0", ctypes.c_double), ("ms_sketch", ctypes.c_double),
+                ("ms_factor", ctypes.c_double), ("ms_refine", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("reserved", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class SketchError(RuntimeError):
@@ -59,6 +76,10 @@ def load():
         "sketch_plan": ([P, i32, i64, i64, ctypes.POINTER(Schedule)], ctypes.c_int),
         "sketch_hash": ([P, i64, i64, P, P, P], ctypes.c_int),
         "sketch_quantize": ([i32, P, P, i64, u64, u32, u64, P], ctypes.c_int),
+        "sketch_solve": ([P, P, i32, i64, i64, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P],
+                         ctypes.c_int),
+        "sketch_qr_f32": ([P, i64, i64, i64, i64, P, P], ctypes.c_int),
+        "sketch_trinv_f32": ([P, i64, i64, P, P, i64, P, P], ctypes.c_int),
         "sketch_last_error": ([], ctypes.c_char_p),
         "sketch_version": ([], ctypes.c_int),
     }

@@ -24,18 +24,40 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = ["/opt/rocm/bin/hipcc", *FLAGS, *sources(), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"
     err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l and l.strip())
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if verbose and err:
-        print(err, file=sys.stderr)
+    return r.returncode, err
+
+
+def build(verbose=False):
+    """Compile each source to an object in parallel, then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        jobs.append((obj, ["/opt/rocm/bin/hipcc", *compile_flags, "-c", src, "-o", obj]))
+    if verbose:
+        for _, cmd in jobs:
+            print(" ".join(cmd), flush=True)
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1, 16)) as ex:
+        results = list(ex.map(lambda j: _run(j[1]), jobs))
+    for (obj, cmd), (rc, err) in zip(jobs, results):
+        if rc != 0:
+            raise RuntimeError("hipcc failed on %s:\n%s" % (cmd[-3], err))
+        if verbose and err:
+            print(err, file=sys.stderr)
+    tmp = LIB + ".tmp"
+    link = ["/opt/rocm/bin/hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, *[o for o, _ in jobs], "-o", tmp]
+    if verbose:
+        print(" ".join(link), flush=True)
+    rc, err = _run(link)
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + err)
     os.replace(tmp, LIB)
     return LIB
 

@@ -172,6 +172,7 @@ int sketch_destroy(sk_handle h)
 {
     if (!h) return SK_OK;
     if (h->ws) (void)hipFree(h->ws);
+    solve_release(h);
     delete h;
     return SK_OK;
 }

@@ -7,6 +7,8 @@
 
 #include "../../include/sketch.h"
 
+namespace sk { struct SolveWs; }
+
 struct sk_sketch {
     int64_t m = 0, d = 0;
     int32_t s = 0;
@@ -17,6 +19,8 @@ struct sk_sketch {
     // FP32 workspace for SK_ACCUMULATE when 1/sqrt(s) is not a power of two
     float *ws = nullptr;
     size_t ws_floats = 0;
+    // device workspace of sketch_solve (allocated on first use)
+    sk::SolveWs *sw = nullptr;
 };
 
 namespace sk {
@@ -69,6 +73,8 @@ hipError_t launch_scale(float *SA, int64_t d, int64_t n, int64_t ldsa, const flo
                         int accumulate, hipStream_t st);
 hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, int64_t count,
                        int32_t *buckets, int8_t *signs, hipStream_t st);
+void solve_release(sk_sketch *h);
+
 hipError_t launch_quantize(int mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
                            uint32_t epoch, uint64_t site0, hipStream_t st);
 

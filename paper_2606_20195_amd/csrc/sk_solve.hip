@@ -1,0 +1,1248 @@
+// Least squares by sketch-and-precondition with FP64 iterative refinement,
+// and the FP32 Householder QR and triangular inverse it is built on.
+//
+// The paper solves the sketched problem min ||SAx - Sb|| with an FP32 reduced
+// QR and a triangular solve (Section 5.1).  Here that solution is only the
+// start: R of the QR is the right preconditioner of LSQR (Paige and Saunders,
+// ACM TOMS 8(1), 1982, Section 4) run in FP32 on the correction equation of
+// FP64 iterative refinement, so the answer is the FP64 least-squares solution
+// for the stored A whatever the precision of the sketch.
+//
+// Device work per solve:
+//   sketch      SA (the handle's mode) and Sb (FP32) into M = [SA | Sb]
+//   factor      blocked Householder QR of M in FP32 (one-workgroup panel
+//               kernel + multi-workgroup trailing update per panel), P = R^-1
+//               and P^T in FP32, x0 = P (Q^T Sb) in FP64
+//   refine      per step one FP64 row pass (r = b - A x, A^T r, norms) and
+//               one row pass per LSQR iteration; a row pass reads A once and
+//               forms both A t and A^T u (the row of A needed for the second
+//               product is the one just read), and its last workgroup to
+//               finish reduces the per-workgroup partials and runs the
+//               O(n^2) vector recurrences, so an LSQR iteration is one launch.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sk_internal.hpp"
+
+namespace sk {
+
+namespace {
+
+constexpr int kT = 1024;           // threads of the row passes and one-workgroup kernels
+constexpr int kWaves = kT / 64;
+constexpr int kUT = 256;           // threads of the QR trailing update
+constexpr int kCB = 8;             // columns per trailing-update workgroup (maximum)
+constexpr int kMaxN = 1024;
+constexpr int64_t kMaxD = 16384;
+
+// Device-resident state of the refinement and of the running LSQR.
+struct SolveState {
+    double fro2;        // ||A||_F^2
+    double bnorm2;      // ||b||^2
+    double rnorm;       // ||b - A x|| of the current x
+    double crit;        // ||A^T r|| / (||A||_F ||r||)
+    double rel;         // ||r|| / ||b||
+    double alpha, rhobar, phibar, anorm2, coef, beta1;
+    double alpha1;      // ||(A P)^T r/||r|| || at the start of the current LSQR run
+    double tol, inner_tol;
+    int32_t outer_done, inner_done, inner_iter, total_inner;
+    int32_t bad, max_inner, pad0, pad1;
+};
+
+// ------------------------------------------------------------ reductions
+
+template <int W>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float sum_lanes(float v, int width)
+{
+    for (int o = 1; o < width; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over all kT threads; every thread receives the total.  `sh` holds kWaves
+// doubles; all threads must call it.
+__device__ double block_sum(double v, double* sh)
+{
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    return t;
+}
+
+// ------------------------------------------------------------ element loads
+
+template <typename AT> struct ET;
+template <> struct ET<float> { static constexpr int C = 4; static constexpr int B = 4; };
+template <> struct ET<__half> { static constexpr int C = 8; static constexpr int B = 2; };
+template <> struct ET<__hip_bfloat16> { static constexpr int C = 8; static constexpr int B = 2; };
+
+template <typename AT> __device__ __forceinline__ float lo16(uint32_t w);
+template <typename AT> __device__ __forceinline__ float hi16(uint32_t w);
+template <> __device__ __forceinline__ float lo16<__half>(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+}
+template <> __device__ __forceinline__ float hi16<__half>(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+template <> __device__ __forceinline__ float lo16<__hip_bfloat16>(uint32_t w) { return __uint_as_float(w << 16); }
+template <> __device__ __forceinline__ float hi16<__hip_bfloat16>(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// C consecutive elements (16 bytes) at byte offset `off` of the buffer.  With
+// vec = false the bytes are read with element-sized loads (any element
+// alignment).  Offsets past the buffer's end read as zero.
+template <typename AT>
+__device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool vec,
+                                           float (&a)[ET<AT>::C])
+{
+    uint32_t w[4];
+    if (vec) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        w[0] = q[0];
+        w[1] = q[1];
+        w[2] = q[2];
+        w[3] = q[3];
+    } else if constexpr (ET<AT>::B == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4u * e), 0, 0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t l = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)(off + 4u * e), 0, 0);
+            const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)(off + 4u * e + 2u), 0, 0);
+            w[e] = (l & 0xFFFFu) | (h << 16);
+        }
+    }
+    if constexpr (ET<AT>::B == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = __uint_as_float(w[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            a[2 * e] = lo16<AT>(w[e]);
+            a[2 * e + 1] = hi16<AT>(w[e]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ row passes
+
+struct RowArgs {
+    const void* A;
+    int64_t lda, m, rpw;       // rows per workgroup
+    int32_t n, vec, mask, first;
+    const double* b;
+    double* x;                 // FP64 solution (n)
+    float* u;                  // m: r in FP32 after a residual pass, then LSQR's unnormalised u
+    float* t;                  // n: P v, the direction of the next LSQR product
+    const float* P;            // n x n, upper triangular
+    const float* PT;           // P^T
+    int64_t ldp;
+    double* v;                 // LSQR vectors (n each)
+    double* w;
+    double* y;
+    double* part;              // per-workgroup partials, stride pst doubles
+    int32_t pst;
+    SolveState* st;
+    uint32_t* ticket;
+};
+
+// Dynamic LDS of a row pass: per-wave column sums, then the epilogue's vectors.
+size_t row_lds_bytes(int n, bool fp64)
+{
+    const size_t pass = (size_t)kWaves * n * (fp64 ? 8 : 4);
+    const size_t epi = (size_t)(3 * (n + 4) + kT + kWaves) * 8;
+    return std::max(pass, epi);
+}
+
+// Reduce `nv` values over the workgroup partials into out[0..nv) (LDS).
+__device__ void reduce_partials(const double* part, int pst, int nwg, int nv, double* out, double* tmp)
+{
+    const int tid = threadIdx.x;
+    if (nv > kT / 2) {
+        for (int j = tid; j < nv; j += kT) {
+            double s = 0.0;
+            for (int wgi = 0; wgi < nwg; ++wgi) s += part[(int64_t)wgi * pst + j];
+            out[j] = s;
+        }
+        __syncthreads();
+        return;
+    }
+    const int parts = kT / nv;
+    if (tid < parts * nv) {
+        const int j = tid % nv, q = tid / nv;
+        double s0 = 0.0, s1 = 0.0;
+        int wgi = q;
+        for (; wgi + parts < nwg; wgi += 2 * parts) {
+            s0 += part[(int64_t)wgi * pst + j];
+            s1 += part[(int64_t)(wgi + parts) * pst + j];
+        }
+        if (wgi < nwg) s0 += part[(int64_t)wgi * pst + j];
+        tmp[tid] = s0 + s1;
+    }
+    __syncthreads();
+    for (int j = tid; j < nv; j += kT) {
+        double s = 0.0;
+        for (int q = 0; q < parts; ++q) s += tmp[q * nv + j];
+        out[j] = s;
+    }
+    __syncthreads();
+}
+
+// out_j = sum_{k <= j} P[k][j] in_k  (P^T times a vector; in, out in LDS)
+__device__ void mv_PT(const float* P, int64_t ldp, int n, const double* in, double* out, double* tmp)
+{
+    const int tid = threadIdx.x;
+    const int parts = kT / n;
+    if (tid < parts * n) {
+        const int j = tid % n, q = tid / n;
+        double s = 0.0;
+        for (int k = q; k <= j; k += parts) s = fma((double)P[(int64_t)k * ldp + j], in[k], s);
+        tmp[tid] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += kT) {
+        double s = 0.0;
+        for (int q = 0; q < parts; ++q) s += tmp[q * n + j];
+        out[j] = s;
+    }
+    __syncthreads();
+}
+
+// out_i = sum_{j >= i} P[i][j] in_j  (P times a vector, read through P^T)
+__device__ void mv_P(const float* PT, int64_t ldp, int n, const double* in, double* out, double* tmp)
+{
+    const int tid = threadIdx.x;
+    const int parts = kT / n;
+    if (tid < parts * n) {
+        const int i = tid % n, q = tid / n;
+        double s = 0.0;
+        for (int j = i + q; j < n; j += parts) s = fma((double)PT[(int64_t)j * ldp + i], in[j], s);
+        tmp[tid] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kT) {
+        double s = 0.0;
+        for (int q = 0; q < parts; ++q) s += tmp[q * n + i];
+        out[i] = s;
+    }
+    __syncthreads();
+}
+
+// True in exactly one workgroup, the last to finish; partials written before
+// the call are visible to it.
+__device__ bool last_workgroup(uint32_t* ticket)
+{
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) *ticket = 0u;
+    return true;
+}
+
+// LSQR start on min ||A P y - r/||r|| ||, given g = A^T r (LDS, FP64) and
+// ||r|| (Paige-Saunders, Section 4, step 1 with beta_1 u_1 = r/||r||).
+__device__ void lsqr_start(const RowArgs& p, double* g, double rnorm, double* sc)
+{
+    const int n = p.n, tid = threadIdx.x;
+    double* q = g + (n + 4);
+    double* tv = q + (n + 4);
+    double* tmp = tv + (n + 4);
+    double* sh = tmp + kT;
+    const double ib = rnorm > 0.0 ? 1.0 / rnorm : 0.0;
+    for (int j = tid; j < n; j += kT) g[j] *= ib;
+    __syncthreads();
+    mv_PT(p.P, p.ldp, n, g, q, tmp);
+    double ss = 0.0;
+    for (int j = tid; j < n; j += kT) ss = fma(q[j], q[j], ss);
+    const double alpha = sqrt(block_sum(ss, sh));
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    for (int j = tid; j < n; j += kT) {
+        const double vj = q[j] * ia;
+        q[j] = vj;
+        p.v[j] = vj;
+        p.w[j] = vj;
+        p.y[j] = 0.0;
+    }
+    __syncthreads();
+    mv_P(p.PT, p.ldp, n, q, tv, tmp);
+    for (int j = tid; j < n; j += kT) p.t[j] = (float)tv[j];
+    if (tid == 0) {
+        SolveState* st = p.st;
+        st->alpha = alpha;
+        st->alpha1 = alpha;
+        st->rhobar = alpha;
+        st->phibar = 1.0;
+        st->anorm2 = 0.0;
+        st->beta1 = rnorm;
+        st->coef = rnorm > 0.0 ? alpha / rnorm : 0.0;
+        st->inner_iter = 0;
+        st->inner_done = (alpha == 0.0 || rnorm == 0.0) ? 1 : 0;
+    }
+    (void)sc;
+}
+
+// FP64 residual pass: r = b - A x, writes r (FP32) into u and reduces A^T r,
+// ||r||^2 (and on the first pass ||A||_F^2, ||b||^2); the last workgroup
+// evaluates the stopping test and starts LSQR.
+template <typename AT, int LR, int CP>
+__global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
+{
+    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 4 ? 1 : 2;
+    extern __shared__ double dsh[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rs = lane / LR, cl = lane % LR;
+    const int n = p.n;
+
+    double xr[CP][C], g[CP][C];
+    int col0[CP];
+#pragma unroll
+    for (int pp = 0; pp < CP; ++pp) {
+        col0[pp] = C * (cl + LR * pp);
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int c = col0[pp] + e;
+            xr[pp][e] = c < n ? p.x[c] : 0.0;
+            g[pp][e] = 0.0;
+        }
+    }
+    const int64_t row0 = (int64_t)blockIdx.x * p.rpw;
+    const int64_t row1 = row0 >= p.m ? row0 : (row0 + p.rpw < p.m ? row0 + p.rpw : p.m);
+    const uint32_t rowbytes = (uint32_t)(p.lda * B);
+    const uint32_t nrec = (uint32_t)((row1 - row0) * rowbytes);
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const char*)p.A + row0 * (int64_t)rowbytes), (short)0, (int)nrec, 0x00020000);
+    const bool vec = p.vec != 0, mask = p.mask != 0, first = p.first != 0;
+    double rr = 0.0, aa = 0.0, bb = 0.0;
+    const int64_t step = (int64_t)kWaves * RW;
+
+    for (int64_t rb = row0 + (int64_t)wave * RW; rb < row1; rb += U * step) {
+        float a[U][CP][C];
+        double bv[U];
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t row = rb + uu * step + rs;
+            const bool valid = row < row1;
+            const uint32_t off = valid ? (uint32_t)(row - row0) * rowbytes : nrec;
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
+            bv[uu] = valid ? p.b[row] : 0.0;
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t row = rb + uu * step + rs;
+            const bool valid = row < row1;
+            double dot = 0.0;
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    if (mask && col0[pp] + e >= n) a[uu][pp][e] = 0.0f;
+                    dot = fma((double)a[uu][pp][e], xr[pp][e], dot);
+                }
+            dot = group_sum<LR>(dot);
+            const double r = valid ? bv[uu] - dot : 0.0;
+            if (valid && cl == 0) p.u[row] = (float)r;
+            if (cl == 0) rr = fma(r, r, rr);
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+                for (int e = 0; e < C; ++e) g[pp][e] = fma(r, (double)a[uu][pp][e], g[pp][e]);
+            if (first) {
+                if (cl == 0) bb = fma(bv[uu], bv[uu], bb);
+#pragma unroll
+                for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+                    for (int e = 0; e < C; ++e) aa = fma((double)a[uu][pp][e], (double)a[uu][pp][e], aa);
+            }
+        }
+    }
+    // column sums: over the RW row slots of the wave, then over the waves
+#pragma unroll
+    for (int o = LR; o < 64; o <<= 1)
+#pragma unroll
+        for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+            for (int e = 0; e < C; ++e) g[pp][e] += __shfl_xor(g[pp][e], o, 64);
+    rr = group_sum<64>(rr);
+    aa = group_sum<64>(aa);
+    bb = group_sum<64>(bb);
+    double* red = dsh;
+    __shared__ double wsum[kWaves][3];
+    if (rs == 0) {
+#pragma unroll
+        for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (col0[pp] + e < n) red[wave * n + col0[pp] + e] = g[pp][e];
+    }
+    if (lane == 0) {
+        wsum[wave][0] = rr;
+        wsum[wave][1] = aa;
+        wsum[wave][2] = bb;
+    }
+    __syncthreads();
+    double* mine = p.part + (int64_t)blockIdx.x * p.pst;
+    for (int j = tid; j < n; j += kT) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kWaves; ++w2) s += red[w2 * n + j];
+        mine[j] = s;
+    }
+    if (tid < 3) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kWaves; ++w2) s += wsum[w2][tid];
+        mine[n + tid] = s;
+    }
+    if (!last_workgroup(p.ticket)) return;
+
+    // ---- epilogue (one workgroup)
+    double* g64 = dsh;                   // n + 3 values
+    double* tmp = dsh + 3 * (n + 4);
+    double* sh = tmp + kT;
+    reduce_partials(p.part, p.pst, gridDim.x, n + 3, g64, tmp);
+    SolveState* st = p.st;
+    if (first && tid == 0) {
+        st->fro2 = g64[n + 1];
+        st->bnorm2 = g64[n + 2];
+    }
+    double gs = 0.0;
+    for (int j = tid; j < n; j += kT) gs = fma(g64[j], g64[j], gs);
+    const double gnorm = sqrt(block_sum(gs, sh));
+    const double fro2 = first ? g64[n + 1] : st->fro2;
+    const double bn2 = first ? g64[n + 2] : st->bnorm2;
+    const double rnorm = sqrt(g64[n]);
+    const double crit = (rnorm > 0.0 && fro2 > 0.0) ? gnorm / (sqrt(fro2) * rnorm) : 0.0;
+    const double rel = bn2 > 0.0 ? rnorm / sqrt(bn2) : 0.0;
+    const bool done = crit <= st->tol || rel <= st->tol;
+    __syncthreads();
+    if (tid == 0) {
+        st->rnorm = rnorm;
+        st->crit = crit;
+        st->rel = rel;
+        st->outer_done = done ? 1 : 0;
+        if (!(crit == crit) || !(rnorm == rnorm)) st->bad = 2;
+    }
+    if (done) return;
+    lsqr_start(p, g64, rnorm, sh);
+}
+
+// One LSQR iteration (Paige-Saunders, Section 4, steps 3-6) on the operator
+// A P: u' = A t - coef u (t = P v, u = beta u' from the previous iteration),
+// A^T u' and ||u'||^2 in the same pass; the last workgroup finishes the
+// iteration and, at termination, adds ||r|| P y to x in FP64.
+template <typename AT, int LR, int CP>
+__global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
+{
+    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 4 ? 1 : (CP == 2 ? 2 : 4);
+    extern __shared__ double dsh[];
+    SolveState* st = p.st;
+    if (st->inner_done != 0 || st->outer_done != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rs = lane / LR, cl = lane % LR;
+    const int n = p.n;
+
+    float tr[CP][C], g[CP][C];
+    int col0[CP];
+#pragma unroll
+    for (int pp = 0; pp < CP; ++pp) {
+        col0[pp] = C * (cl + LR * pp);
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int c = col0[pp] + e;
+            tr[pp][e] = c < n ? p.t[c] : 0.0f;
+            g[pp][e] = 0.0f;
+        }
+    }
+    const float coef = (float)st->coef;
+    const int64_t row0 = (int64_t)blockIdx.x * p.rpw;
+    const int64_t row1 = row0 >= p.m ? row0 : (row0 + p.rpw < p.m ? row0 + p.rpw : p.m);
+    const uint32_t rowbytes = (uint32_t)(p.lda * B);
+    const uint32_t nrec = (uint32_t)((row1 - row0) * rowbytes);
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)((const char*)p.A + row0 * (int64_t)rowbytes), (short)0, (int)nrec, 0x00020000);
+    const bool vec = p.vec != 0, mask = p.mask != 0;
+    float ss = 0.0f;
+    const int64_t step = (int64_t)kWaves * RW;
+
+    for (int64_t rb = row0 + (int64_t)wave * RW; rb < row1; rb += U * step) {
+        float a[U][CP][C];
+        float uo[U];
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t row = rb + uu * step + rs;
+            const bool valid = row < row1;
+            const uint32_t off = valid ? (uint32_t)(row - row0) * rowbytes : nrec;
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
+            uo[uu] = valid ? p.u[row] : 0.0f;
+        }
+#pragma unroll
+        for (int uu = 0; uu < U; ++uu) {
+            const int64_t row = rb + uu * step + rs;
+            const bool valid = row < row1;
+            float dot = 0.0f;
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    if (mask && col0[pp] + e >= n) a[uu][pp][e] = 0.0f;
+                    dot = __builtin_fmaf(a[uu][pp][e], tr[pp][e], dot);
+                }
+            dot = group_sum<LR>(dot);
+            const float un = valid ? __builtin_fmaf(-coef, uo[uu], dot) : 0.0f;
+            if (valid && cl == 0) p.u[row] = un;
+            if (cl == 0) ss = __builtin_fmaf(un, un, ss);
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+                for (int e = 0; e < C; ++e) g[pp][e] = __builtin_fmaf(un, a[uu][pp][e], g[pp][e]);
+        }
+    }
+#pragma unroll
+    for (int o = LR; o < 64; o <<= 1)
+#pragma unroll
+        for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+            for (int e = 0; e < C; ++e) g[pp][e] += __shfl_xor(g[pp][e], o, 64);
+    ss = group_sum<64>(ss);
+    float* red = (float*)dsh;
+    __shared__ float wss[kWaves];
+    if (rs == 0) {
+#pragma unroll
+        for (int pp = 0; pp < CP; ++pp)
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (col0[pp] + e < n) red[wave * n + col0[pp] + e] = g[pp][e];
+    }
+    if (lane == 0) wss[wave] = ss;
+    __syncthreads();
+    double* mine = p.part + (int64_t)blockIdx.x * p.pst;
+    for (int j = tid; j < n; j += kT) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kWaves; ++w2) s += (double)red[w2 * n + j];
+        mine[j] = s;
+    }
+    if (tid == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kWaves; ++w2) s += (double)wss[w2];
+        mine[n] = s;
+    }
+    if (!last_workgroup(p.ticket)) return;
+
+    // ---- epilogue (one workgroup)
+    double* g64 = dsh;                       // A^T u' (n), ||u'||^2
+    double* q = g64 + (n + 4);
+    double* tv = q + (n + 4);
+    double* tmp = tv + (n + 4);
+    double* sh = tmp + kT;
+    reduce_partials(p.part, p.pst, gridDim.x, n + 1, g64, tmp);
+    const double beta = sqrt(g64[n]);
+    const double alpha_old = st->alpha;
+    const double anorm2 = st->anorm2 + alpha_old * alpha_old + beta * beta;
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int j = tid; j < n; j += kT) g64[j] *= ib;
+    __syncthreads();
+    mv_PT(p.P, p.ldp, n, g64, q, tmp);
+    double qs = 0.0;
+    for (int j = tid; j < n; j += kT) {
+        const double qj = q[j] - beta * p.v[j];
+        q[j] = qj;
+        qs = fma(qj, qj, qs);
+    }
+    const double alpha = sqrt(block_sum(qs, sh));
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    // plane rotation (no damping)
+    const double rhobar0 = st->rhobar, phibar0 = st->phibar;
+    const double rho = hypot(rhobar0, beta);
+    const double c = rho > 0.0 ? rhobar0 / rho : 1.0;
+    const double sn = rho > 0.0 ? beta / rho : 0.0;
+    const double theta = sn * alpha;
+    const double rhobar = -c * alpha;
+    const double phi = c * phibar0;
+    const double phibar = sn * phibar0;
+    const double t1 = rho > 0.0 ? phi / rho : 0.0;
+    const double t2 = rho > 0.0 ? -theta / rho : 0.0;
+    for (int j = tid; j < n; j += kT) {
+        const double vj = q[j] * ia;
+        const double wj = p.w[j];
+        p.y[j] = fma(t1, wj, p.y[j]);
+        p.w[j] = fma(t2, wj, vj);
+        p.v[j] = vj;
+        q[j] = vj;
+    }
+    const int iter = st->inner_iter + 1;
+    const double itol = st->inner_tol;
+    // Stopping: the correction problem's normal-equations residual
+    // ||(A P)^T (r^ - A P y)|| = phibar alpha |c| (Paige-Saunders, Section 5)
+    // has fallen by inner_tol from its start alpha_1, or (consistent
+    // corrections) the residual estimate phibar has fallen by inner_tol.  The
+    // test is relative to the start, not to ||r^||: near the solution r^ is
+    // almost orthogonal to the range of A, and a test relative to ||r^|| would
+    // stop after one iteration.
+    const double test2 = st->alpha1 > 0.0 ? phibar * alpha * fabs(c) / st->alpha1 : 0.0;
+    const double test1 = phibar;
+    const bool done = beta == 0.0 || alpha == 0.0 || test2 <= itol || test1 <= itol || iter >= st->max_inner;
+    __syncthreads();
+    if (!done) {
+        mv_P(p.PT, p.ldp, n, q, tv, tmp);
+        for (int j = tid; j < n; j += kT) p.t[j] = (float)tv[j];
+    } else {
+        // x += ||r|| P y in FP64
+        for (int j = tid; j < n; j += kT) q[j] = p.y[j];
+        __syncthreads();
+        mv_P(p.PT, p.ldp, n, q, tv, tmp);
+        const double scale = st->beta1;
+        for (int j = tid; j < n; j += kT) p.x[j] = fma(scale, tv[j], p.x[j]);
+    }
+    if (tid == 0) {
+        st->alpha = alpha;
+        st->rhobar = rhobar;
+        st->phibar = phibar;
+        st->anorm2 = anorm2;
+        st->coef = beta > 0.0 ? alpha / beta : 0.0;
+        st->inner_iter = iter;
+        st->total_inner += 1;
+        st->inner_done = done ? 1 : 0;
+        if (!(alpha == alpha) || !(beta == beta)) st->bad = 2;
+    }
+}
+
+// ------------------------------------------------------------ QR (FP32)
+
+// Householder factorisation of the panel M[k0:rows, k0:k0+nb] in LDS by one
+// workgroup (LAPACK slarfg convention: beta = -sign(x0) ||x||, v[0] = 1).
+__global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
+                                                       int32_t nb, float* tau)
+{
+    extern __shared__ float pan[];
+    __shared__ float s_tau[32];
+    const int rows = rows_total - k0;
+    const int ldl = rows | 1;            // odd column stride: the transposing stores hit distinct banks
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < rows * nb; idx += kT) {
+        const int r = idx / nb, c = idx - r * nb;
+        pan[c * ldl + r] = M[(int64_t)(k0 + r) * ldm + k0 + c];
+    }
+    __syncthreads();
+    const int G = nb > 16 ? 32 : 64;     // lanes per column group: kT / G >= nb groups
+    const int grp = tid / G, gl = tid % G;
+    for (int j = 0; j < nb; ++j) {
+        if (grp == j) {
+            float* x = pan + j * ldl;
+            float sig = 0.0f;
+            for (int r = j + 1 + gl; r < rows; r += G) sig = __builtin_fmaf(x[r], x[r], sig);
+            sig = sum_lanes(sig, G);
+            const float x0 = x[j];
+            float t = 0.0f, beta = x0;
+            if (sig > 0.0f) {
+                beta = -copysignf(sqrtf(__builtin_fmaf(x0, x0, sig)), x0);
+                t = (beta - x0) / beta;
+                const float scal = 1.0f / (x0 - beta);
+                for (int r = j + 1 + gl; r < rows; r += G) x[r] *= scal;
+            }
+            if (gl == 0) {
+                x[j] = beta;
+                s_tau[j] = t;
+            }
+        }
+        __syncthreads();
+        if (grp > j && grp < nb) {
+            const float t = s_tau[j];
+            if (t != 0.0f) {
+                const float* v = pan + j * ldl;
+                float* yc = pan + grp * ldl;
+                float w = gl == 0 ? yc[j] : 0.0f;
+                for (int r = j + 1 + gl; r < rows; r += G) w = __builtin_fmaf(v[r], yc[r], w);
+                w = sum_lanes(w, G) * t;
+                if (gl == 0) yc[j] -= w;
+                for (int r = j + 1 + gl; r < rows; r += G) yc[r] = __builtin_fmaf(-w, v[r], yc[r]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < rows * nb; idx += kT) {
+        const int r = idx / nb, c = idx - r * nb;
+        M[(int64_t)(k0 + r) * ldm + k0 + c] = pan[c * ldl + r];
+    }
+    if (tid < nb) tau[k0 + tid] = s_tau[tid];
+}
+
+// Apply the panel's reflectors H_{k0} .. H_{k0+nb-1} to columns
+// [c0, c0 + ncols) of M; each workgroup owns cb columns held in LDS.
+__global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
+                                                         int32_t nb, int32_t c0, int32_t ncols, int32_t cb,
+                                                         const float* tau)
+{
+    extern __shared__ float blk[];       // [rows][cb]
+    __shared__ float red[2][kUT / 64][kCB];
+    const int rows = rows_total - k0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cbase = c0 + blockIdx.x * cb;
+    const int nc = min(cb, c0 + ncols - cbase);
+    for (int idx = tid; idx < rows * cb; idx += kUT) {
+        const int r = idx / cb, c = idx - r * cb;
+        blk[idx] = c < nc ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        const float t = tau[k0 + j];
+        if (t == 0.0f) continue;
+        float acc[kCB];
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
+        for (int r = tid; r < rows; r += kUT) {
+            if (r < j) continue;
+            const float v = r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c)
+                if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * cb + c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) {
+            acc[c] = group_sum<64>(acc[c]);
+            if (lane == 0) red[j & 1][wave][c] = acc[c];
+        }
+        __syncthreads();
+        float w[kCB];
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) {
+            float s = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kUT / 64; ++q) s += red[j & 1][q][c];
+            w[c] = s * t;
+        }
+        for (int r = tid; r < rows; r += kUT) {
+            if (r < j) continue;
+            const float v = r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c)
+                if (c < cb) blk[r * cb + c] = __builtin_fmaf(-w[c], v, blk[r * cb + c]);
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < rows * cb; idx += kUT) {
+        const int r = idx / cb, c = idx - r * cb;
+        if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[idx];
+    }
+}
+
+// P = R^-1 (and P^T) by back substitution: wave w of workgroup b computes
+// column j = 16 b + w; rows of R are staged through LDS 16 at a time.
+__global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, int32_t n, float* P, float* PT,
+                                                    int64_t ldp, int32_t* bad)
+{
+    extern __shared__ float rp[];        // [16][J]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = blockIdx.x * kWaves + wave;
+    const int J = min(n, (int)(blockIdx.x + 1) * kWaves);
+    float xv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xv[q] = 0.0f;
+    bool ok = true;
+    for (int hi = J - 1; hi >= 0; hi -= 16) {
+        const int lo = max(0, hi - 15);
+        __syncthreads();
+        for (int idx = tid; idx < (hi - lo + 1) * J; idx += kT) {
+            const int rr = idx / J, k = idx - rr * J;
+            const int i = lo + rr;
+            rp[idx] = k >= i ? R[(int64_t)i * ldr + k] : 0.0f;
+        }
+        __syncthreads();
+        if (j < n) {
+            for (int i = min(hi, j); i >= lo; --i) {
+                const float* row = rp + (i - lo) * J;
+                float s = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int k = lane + 64 * q;
+                    if (k > i && k <= j) s = __builtin_fmaf(row[k], xv[q], s);
+                }
+                s = group_sum<64>(s);
+                const float dgl = row[i];
+                const float xi = ((i == j ? 1.0f : 0.0f) - s) / dgl;
+                if (!(dgl != 0.0f) || !(fabsf(xi) <= 3.0e38f)) ok = false;
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (lane + 64 * q == i) xv[q] = xi;
+            }
+        }
+    }
+    if (j < n) {
+        for (int i = lane; i < n; i += 64) {
+            float val = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (lane + 64 * q == i) val = xv[q];
+            if (i > j) val = 0.0f;
+            P[(int64_t)i * ldp + j] = val;
+            PT[(int64_t)j * ldp + i] = val;
+        }
+        if (!ok && lane == 0) *bad = 1;
+    }
+}
+
+// x = P z in FP64, z = the first n entries of column zc of M (Q^T Sb).
+__global__ __launch_bounds__(kT) void x0_kernel(const float* PT, int64_t ldp, int32_t n, const float* M,
+                                                 int64_t ldm, int32_t zc, double* x)
+{
+    __shared__ double z[kMaxN];
+    __shared__ double out[kMaxN];
+    __shared__ double tmp[kT];
+    for (int j = threadIdx.x; j < n; j += kT) z[j] = (double)M[(int64_t)j * ldm + zc];
+    __syncthreads();
+    mv_P(PT, ldp, n, z, out, tmp);
+    for (int j = threadIdx.x; j < n; j += kT) x[j] = out[j];
+}
+
+__global__ void cast_f64_f32_kernel(const double* in, float* out, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+__global__ void f16_to_f32_kernel(const uint16_t* in, int64_t ldi, float* out, int64_t ldo, int64_t rows,
+                                  int32_t cols)
+{
+    const int64_t total = rows * cols;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols;
+        const int c = (int)(i - r * cols);
+        out[r * ldo + c] = (float)__builtin_bit_cast(_Float16, in[r * ldi + c]);
+    }
+}
+
+__global__ void init_state_kernel(SolveState* st, double tol, double inner_tol, int32_t max_inner, uint32_t* ticket)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        SolveState s{};
+        s.tol = tol;
+        s.inner_tol = inner_tol;
+        s.max_inner = max_inner;
+        s.inner_done = 1;
+        *st = s;
+        *ticket = 0u;
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+int hip_err(hipError_t e, const char* what)
+{
+    return set_error(SK_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int panel_width(int64_t rows)
+{
+    const int64_t ldl = rows | 1;
+    for (int nb : {32, 16, 8, 4, 2, 1})
+        if (ldl * nb * 4 <= 150 * 1024) return nb;
+    return 0;
+}
+
+int update_cols(int64_t rows)
+{
+    for (int cb : {kCB, 4, 2, 1})
+        if (rows * cb * 4 <= 128 * 1024) return cb;
+    return 0;
+}
+
+hipError_t set_lds(const void* fn, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// In-place QR of the first k columns of M (rows x cols).
+hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float* tau, hipStream_t st)
+{
+    hipError_t e;
+    const int cb = update_cols(rows);
+    for (int64_t k0 = 0; k0 < k; ) {
+        const int64_t prow = rows - k0;
+        const int nb = (int)std::min<int64_t>(panel_width(prow), k - k0);
+        const size_t lds = (size_t)(prow | 1) * nb * 4;
+        if ((e = set_lds((const void*)qr_panel_kernel, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kT), lds, st, M, ldm, (int32_t)rows, (int32_t)k0,
+                           (int32_t)nb, tau);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t c0 = k0 + nb, ncols = cols - c0;
+        if (ncols > 0) {
+            const size_t ulds = (size_t)prow * cb * 4;
+            if ((e = set_lds((const void*)qr_update_kernel, ulds)) != hipSuccess) return e;
+            hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((ncols + cb - 1) / cb)), dim3(kUT), ulds, st, M,
+                               ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0, (int32_t)ncols,
+                               (int32_t)cb, (const float*)tau);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        k0 += nb;
+    }
+    return hipSuccess;
+}
+
+hipError_t run_trinv(const float* R, int64_t ldr, int64_t n, float* P, float* PT, int64_t ldp, int32_t* bad,
+                     hipStream_t st)
+{
+    const int64_t grid = (n + kWaves - 1) / kWaves;
+    const size_t lds = (size_t)16 * std::min<int64_t>(n, grid * kWaves) * 4;
+    hipError_t e = set_lds((const void*)trinv_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trinv_kernel, dim3((unsigned)grid), dim3(kT), lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad);
+    return hipGetLastError();
+}
+
+// Row-pass geometry: C elements (16 bytes) per lane chunk, LR lanes per row,
+// CP chunks per lane.
+struct Geo {
+    int LR = 0, CP = 0, mask = 0;
+};
+
+Geo row_geometry(int esz, int64_t n)
+{
+    const int C = 16 / esz;
+    const int64_t nc = (n + C - 1) / C;
+    Geo g;
+    if (nc <= 64) {
+        int lr = 1;
+        while (lr < nc) lr <<= 1;
+        g.LR = lr;
+        g.CP = 1;
+    } else {
+        g.LR = 64;
+        g.CP = nc <= 128 ? 2 : 4;
+    }
+    g.mask = ((int64_t)g.LR * g.CP * C != n) ? 1 : 0;
+    return g;
+}
+
+template <typename AT, int LR, int CP>
+hipError_t launch_rows_t(bool resid, const RowArgs& a, int nwg, hipStream_t st)
+{
+    const size_t lds = row_lds_bytes(a.n, resid);
+    const void* fn = resid ? (const void*)resid_pass<AT, LR, CP> : (const void*)lsqr_pass<AT, LR, CP>;
+    hipError_t e = set_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    if (resid)
+        hipLaunchKernelGGL((resid_pass<AT, LR, CP>), dim3(nwg), dim3(kT), lds, st, a);
+    else
+        hipLaunchKernelGGL((lsqr_pass<AT, LR, CP>), dim3(nwg), dim3(kT), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename AT>
+hipError_t launch_rows_g(bool resid, const Geo& g, const RowArgs& a, int nwg, hipStream_t st)
+{
+    if (g.CP == 1) {
+        switch (g.LR) {
+            case 1: return launch_rows_t<AT, 1, 1>(resid, a, nwg, st);
+            case 2: return launch_rows_t<AT, 2, 1>(resid, a, nwg, st);
+            case 4: return launch_rows_t<AT, 4, 1>(resid, a, nwg, st);
+            case 8: return launch_rows_t<AT, 8, 1>(resid, a, nwg, st);
+            case 16: return launch_rows_t<AT, 16, 1>(resid, a, nwg, st);
+            case 32: return launch_rows_t<AT, 32, 1>(resid, a, nwg, st);
+            default: return launch_rows_t<AT, 64, 1>(resid, a, nwg, st);
+        }
+    }
+    if (g.CP == 2) return launch_rows_t<AT, 64, 2>(resid, a, nwg, st);
+    if constexpr (ET<AT>::B == 4) return launch_rows_t<AT, 64, 4>(resid, a, nwg, st);
+    return hipErrorInvalidValue;   // 16-bit rows of n <= 1024 need at most two chunks per lane
+}
+
+hipError_t launch_rows(int a_dtype, bool resid, const Geo& g, const RowArgs& a, int nwg, hipStream_t st)
+{
+    if (a_dtype == SK_F32) return launch_rows_g<float>(resid, g, a, nwg, st);
+    if (a_dtype == SK_F16) return launch_rows_g<__half>(resid, g, a, nwg, st);
+    return launch_rows_g<__hip_bfloat16>(resid, g, a, nwg, st);
+}
+
+}  // namespace
+
+// Device workspace of sketch_solve, grown on demand.
+struct SolveWs {
+    int device = -1;
+    void* base = nullptr;
+    size_t bytes = 0;
+    SolveState* host = nullptr;          // pinned copy of the state
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    sk_sketch hb;                        // FP32 sketch of b with the same S
+};
+
+void solve_release(sk_sketch* h)
+{
+    if (!h || !h->sw) return;
+    SolveWs* w = h->sw;
+    if (w->base) (void)hipFree(w->base);
+    if (w->host) (void)hipHostFree(w->host);
+    for (hipEvent_t& e : w->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (w->hb.ws) (void)hipFree(w->hb.ws);
+    delete w;
+    h->sw = nullptr;
+}
+
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+int sketch_qr_f32(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float* tau, void* stream)
+{
+    if (!M || !tau) return set_error(SK_EINVAL, "NULL argument");
+    if (rows < 1 || cols < 1 || ldm < cols || k < 0 || k > rows || k > cols)
+        return set_error(SK_EINVAL, "bad shape rows=%lld cols=%lld ldm=%lld k=%lld", (long long)rows,
+                         (long long)cols, (long long)ldm, (long long)k);
+    if (rows > kMaxD || cols > kMaxN + 1)
+        return set_error(SK_EUNSUPPORTED, "rows <= %lld and cols <= %d", (long long)kMaxD, kMaxN + 1);
+    if (k == 0) return SK_OK;
+    hipError_t e = run_qr(M, rows, cols, ldm, k, tau, (hipStream_t)stream);
+    return e == hipSuccess ? SK_OK : hip_err(e, "QR kernels");
+}
+
+int sketch_trinv_f32(const float* R, int64_t n, int64_t ldr, float* P, float* PT, int64_t ldp, int32_t* bad,
+                     void* stream)
+{
+    if (!R || !P || !PT || !bad) return set_error(SK_EINVAL, "NULL argument");
+    if (n < 1 || n > kMaxN || ldr < n || ldp < n) return set_error(SK_EINVAL, "bad shape n=%lld", (long long)n);
+    hipError_t e = run_trinv(R, ldr, n, P, PT, ldp, bad, (hipStream_t)stream);
+    return e == hipSuccess ? SK_OK : hip_err(e, "inverse kernel");
+}
+
+int sketch_solve(sk_handle h, const void* A, int32_t a_dtype, int64_t n, int64_t lda, const double* b, double* x,
+                 const sk_solve_opts* opts, sk_solve_info* info, void* stream)
+{
+    if (!h) return set_error(SK_EINVAL, "handle is NULL");
+    const int esz = a_dtype == SK_F32 ? 4 : (a_dtype == SK_F16 || a_dtype == SK_BF16) ? 2 : 0;
+    if (!esz) return set_error(SK_EINVAL, "unknown element type %d", a_dtype);
+    if (n < 1 || lda < n) return set_error(SK_EINVAL, "bad shape n=%lld lda=%lld", (long long)n, (long long)lda);
+    if (n > h->d) return set_error(SK_EINVAL, "n = %lld exceeds the sketch size d = %lld", (long long)n,
+                                   (long long)h->d);
+    if (n > kMaxN) return set_error(SK_EUNSUPPORTED, "n = %lld > %d", (long long)n, kMaxN);
+    if (h->d > kMaxD) return set_error(SK_EUNSUPPORTED, "d = %lld > %lld", (long long)h->d, (long long)kMaxD);
+    if (!A || !b || !x) return set_error(SK_EINVAL, "NULL array");
+    if ((uintptr_t)A % (uintptr_t)esz) return set_error(SK_EINVAL, "A is not element aligned");
+    if (((uintptr_t)b | (uintptr_t)x) & 7u) return set_error(SK_EINVAL, "b and x must be 8-byte aligned");
+    sk_solve_opts o{};
+    if (opts) {
+        o = *opts;
+        for (int i = 0; i < 3; ++i)
+            if (o.reserved[i]) return set_error(SK_EINVAL, "reserved option fields must be zero");
+        if (o.tol < 0 || o.inner_tol < 0 || o.max_refine < 0 || o.max_inner < 0)
+            return set_error(SK_EINVAL, "negative option");
+    }
+    if (o.tol == 0) o.tol = 1e-10;
+    if (o.inner_tol == 0) o.inner_tol = 1e-6;
+    if (o.max_refine == 0) o.max_refine = 10;
+    if (o.max_inner == 0) o.max_inner = 100;
+
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+    const int64_t m = h->m, d = h->d;
+    const bool f16 = h->rounding != SK_ACC_F32;
+    const int64_t ldm = n + 1;
+    const int64_t ld16 = (n + 1) / 2 * 2;
+    const int64_t nwg0 = std::max<int64_t>(1, std::min<int64_t>(dev.cus, (m + 1023) / 1024));
+    const int64_t rpw = (m + nwg0 - 1) / nwg0;
+    const int nwg = (int)((m + rpw - 1) / rpw);     // every workgroup owns at least one row
+    if (rpw * lda * esz >= ((int64_t)1 << 31))
+        return set_error(SK_EUNSUPPORTED, "rows per workgroup span more than 2 GiB");
+    const int pst = (int)((n + 3 + 3) / 4 * 4);
+    const Geo geo = row_geometry(esz, n);
+
+    // ---- workspace layout
+    size_t off = 0;
+    auto take = [&](size_t b2) { const size_t at = off; off = align_up(off + b2, 256); return at; };
+    const size_t oM = take((size_t)d * ldm * 4);
+    const size_t o16 = f16 ? take((size_t)d * ld16 * 2) : 0;
+    const size_t ob32 = take((size_t)m * 4);
+    const size_t ou = take((size_t)m * 4);
+    const size_t oP = take((size_t)n * n * 4);
+    const size_t oPT = take((size_t)n * n * 4);
+    const size_t otau = take((size_t)n * 4 + 4);
+    const size_t ot = take((size_t)n * 4);
+    const size_t ov = take((size_t)n * 8);
+    const size_t ow = take((size_t)n * 8);
+    const size_t oy = take((size_t)n * 8);
+    const size_t opart = take((size_t)nwg * pst * 8);
+    const size_t ost = take(sizeof(SolveState));
+    const size_t otk = take(64);
+    const size_t total = off;
+
+    hipError_t e;
+    if (!h->sw) {
+        h->sw = new (std::nothrow) SolveWs;
+        if (!h->sw) return set_error(SK_ENOMEM, "out of host memory");
+        SolveWs* w = h->sw;
+        w->hb.m = h->m;
+        w->hb.d = h->d;
+        w->hb.s = h->s;
+        w->hb.seed = h->seed;
+        w->hb.rounding = SK_ACC_F32;
+        if ((e = hipHostMalloc((void**)&w->host, sizeof(SolveState), hipHostMallocDefault)) != hipSuccess) {
+            w->host = nullptr;
+            return set_error(SK_ENOMEM, "pinned status: %s", hipGetErrorString(e));
+        }
+        for (hipEvent_t& ev : w->ev)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_err(e, "hipEventCreate");
+    }
+    SolveWs* w = h->sw;
+    if (w->bytes < total || w->device != dev.device) {
+        if (w->base) (void)hipFree(w->base);
+        w->base = nullptr;
+        w->bytes = 0;
+        if ((e = hipMalloc(&w->base, total)) != hipSuccess)
+            return set_error(SK_ENOMEM, "solve workspace of %zu bytes: %s", total, hipGetErrorString(e));
+        w->bytes = total;
+        w->device = dev.device;
+    }
+    char* base = (char*)w->base;
+    float* Mw = (float*)(base + oM);
+    uint16_t* SA16 = (uint16_t*)(base + o16);
+    float* b32 = (float*)(base + ob32);
+    hipStream_t st = (hipStream_t)stream;
+
+    RowArgs ra{};
+    ra.A = A;
+    ra.lda = lda;
+    ra.m = m;
+    ra.rpw = rpw;
+    ra.n = (int32_t)n;
+    ra.vec = ((lda * esz) % 16 == 0 && (uintptr_t)A % 16 == 0) ? 1 : 0;
+    ra.mask = geo.mask;
+    ra.b = b;
+    ra.x = x;
+    ra.u = (float*)(base + ou);
+    ra.t = (float*)(base + ot);
+    ra.P = (const float*)(base + oP);
+    ra.PT = (const float*)(base + oPT);
+    ra.ldp = n;
+    ra.v = (double*)(base + ov);
+    ra.w = (double*)(base + ow);
+    ra.y = (double*)(base + oy);
+    ra.part = (double*)(base + opart);
+    ra.pst = pst;
+    ra.st = (SolveState*)(base + ost);
+    ra.ticket = (uint32_t*)(base + otk);
+    float* tau = (float*)(base + otau);
+    int32_t* bad = &ra.st->bad;
+
+    // ---- sketch
+    if ((e = hipEventRecord(w->ev[0], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, st, ra.st, o.tol, o.inner_tol, o.max_inner,
+                       ra.ticket);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "init kernel");
+    if (f16) {
+        rc = sketch_apply(h, A, a_dtype, m, n, lda, 0, SA16, ld16, 0, o.round_epoch, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(f16_to_f32_kernel, dim3(256), dim3(256), 0, st, (const uint16_t*)SA16, ld16, Mw, ldm, d,
+                           (int32_t)n);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "convert kernel");
+    } else {
+        rc = sketch_apply(h, A, a_dtype, m, n, lda, 0, Mw, ldm, 0, o.round_epoch, stream);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(1024), dim3(256), 0, st, b, b32, m);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "cast kernel");
+    rc = sketch_apply(&w->hb, b32, SK_F32, m, 1, 1, 0, Mw + n, ldm, 0, 0, stream);
+    if (rc) return rc;
+    if ((e = hipEventRecord(w->ev[1], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
+
+    // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
+    if ((e = run_qr(Mw, d, n + 1, ldm, n, tau, st)) != hipSuccess) return hip_err(e, "QR kernels");
+    if ((e = run_trinv(Mw, ldm, n, (float*)ra.P, (float*)ra.PT, n, bad, st)) != hipSuccess)
+        return hip_err(e, "inverse kernel");
+    hipLaunchKernelGGL(x0_kernel, dim3(1), dim3(kT), 0, st, ra.PT, (int64_t)n, (int32_t)n, (const float*)Mw, ldm,
+                       (int32_t)n, x);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "x0 kernel");
+    if ((e = hipEventRecord(w->ev[2], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
+
+    // ---- refine
+    auto read_state = [&]() -> int {
+        hipError_t e2 = hipMemcpyAsync(w->host, ra.st, sizeof(SolveState), hipMemcpyDeviceToHost, st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2 == hipSuccess ? SK_OK : hip_err(e2, "reading the solver state");
+    };
+    double rel0 = 0.0;
+    int steps = 0;
+    bool converged = false;
+    for (int k = 0;; ++k) {
+        ra.first = k == 0 ? 1 : 0;
+        if ((e = launch_rows(a_dtype, true, geo, ra, nwg, st)) != hipSuccess) return hip_err(e, "residual pass");
+        if ((rc = read_state())) return rc;
+        if (w->host->bad) return set_error(SK_EINVAL, "SA is numerically rank deficient (zero or non-finite pivot)");
+        if (k == 0) rel0 = w->host->rel;
+        steps = k;
+        if (w->host->outer_done) {
+            converged = true;
+            break;
+        }
+        if (k == o.max_refine) break;
+        ra.first = 0;
+        int launched = 0;
+        while (launched < o.max_inner) {
+            const int batch = std::min(8, o.max_inner - launched);
+            for (int i = 0; i < batch; ++i)
+                if ((e = launch_rows(a_dtype, false, geo, ra, nwg, st)) != hipSuccess) return hip_err(e, "LSQR pass");
+            launched += batch;
+            if ((rc = read_state())) return rc;
+            if (w->host->inner_done) break;
+        }
+        if (w->host->bad) return set_error(SK_EINVAL, "LSQR produced a non-finite value");
+    }
+    if ((e = hipEventRecord(w->ev[3], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
+    if ((e = hipEventSynchronize(w->ev[3])) != hipSuccess) return hip_err(e, "hipEventSynchronize");
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->converged = converged ? 1 : 0;
+        info->refine_steps = steps;
+        info->inner_iters = w->host->total_inner;
+        info->crit = w->host->crit;
+        info->rel_residual = w->host->rel;
+        info->rel_residual_x0 = rel0;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) info->ms_sketch = ms;
+        if (hipEventElapsedTime(&ms, w->ev[1], w->ev[2]) == hipSuccess) info->ms_factor = ms;
+        if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) info->ms_refine = ms;
+        if (hipEventElapsedTime(&ms, w->ev[0], w->ev[3]) == hipSuccess) info->ms_total = ms;
+    }
+    if (!converged)
+        return set_error(SK_ENOTCONV, "not converged after %d refinement steps: criterion %.3e > %.3e", steps,
+                         w->host->crit, o.tol);
+    return SK_OK;
+}
+
+}  // extern "C"

@@ -112,3 +112,42 @@ def test_debug_exports_validation(lib):
     assert lib.sketch_quantize(2, None, FAKE, 3, 0, 0, 0, None) == _lib.EINVAL
     assert lib.sketch_quantize(2, None, None, 0, 0, 0, 0, None) == 0
     lib.sketch_destroy(h)
+
+
+def test_solve_validation(lib):
+    rc, h = _create(lib, m=1000, d=64, s=4, rounding=1)
+    O = _lib.SolveOpts
+    sv = lambda **kw: lib.sketch_solve(   # noqa: E731
+        kw.get("h", h), kw.get("A", FAKE), kw.get("dt", 1), kw.get("n", 8), kw.get("lda", 8),
+        kw.get("b", FAKE), kw.get("x", FAKE), kw.get("opts", None), None, None)
+    assert sv(h=None) == _lib.EINVAL
+    assert sv(dt=5) == _lib.EINVAL
+    assert sv(n=0) == _lib.EINVAL
+    assert sv(lda=4) == _lib.EINVAL
+    assert sv(n=65, lda=65) == _lib.EINVAL                     # n > d
+    assert sv(A=None) == _lib.EINVAL
+    assert sv(b=None) == _lib.EINVAL
+    assert sv(x=ctypes.c_void_p(0x10004)) == _lib.EINVAL       # x not 8-byte aligned
+    assert sv(A=ctypes.c_void_p(0x10001)) == _lib.EINVAL       # A not element aligned
+    bad = O()
+    bad.reserved[1] = 3
+    assert sv(opts=ctypes.byref(bad)) == _lib.EINVAL
+    assert sv(opts=ctypes.byref(O(-1.0))) == _lib.EINVAL
+    assert sv(opts=ctypes.byref(O(0.0, 0.0, -2))) == _lib.EINVAL
+    lib.sketch_destroy(h)
+    rc, hbig = _create(lib, m=100000, d=4096, s=4, rounding=0)
+    assert lib.sketch_solve(hbig, FAKE, 0, 2000, 2000, FAKE, FAKE, None, None, None) == _lib.EUNSUPPORTED
+    lib.sketch_destroy(hbig)
+
+
+def test_qr_trinv_validation(lib):
+    assert lib.sketch_qr_f32(None, 10, 4, 4, 4, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_qr_f32(FAKE, 10, 4, 3, 4, FAKE, None) == _lib.EINVAL   # ldm < cols
+    assert lib.sketch_qr_f32(FAKE, 3, 4, 4, 4, FAKE, None) == _lib.EINVAL    # k > rows
+    assert lib.sketch_qr_f32(FAKE, 10, 4, 4, 5, FAKE, None) == _lib.EINVAL   # k > cols
+    assert lib.sketch_qr_f32(FAKE, 20000, 4, 4, 4, FAKE, None) == _lib.EUNSUPPORTED
+    assert lib.sketch_qr_f32(FAKE, 10, 4, 4, 0, FAKE, None) == 0             # nothing to factor
+    assert lib.sketch_trinv_f32(FAKE, 0, 4, FAKE, FAKE, 4, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_trinv_f32(FAKE, 2000, 2000, FAKE, FAKE, 2000, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_trinv_f32(FAKE, 8, 7, FAKE, FAKE, 8, FAKE, None) == _lib.EINVAL
+    assert lib.sketch_trinv_f32(FAKE, 8, 8, FAKE, None, 8, FAKE, None) == _lib.EINVAL

@@ -1,0 +1,236 @@
+"""GPU parity of the least-squares path: FP32 Householder QR, the triangular
+inverse used as preconditioner, and sketch_solve against the FP64 oracle.
+
+Tolerances.
+  QR: FP32 Householder QR is backward stable, ||dR|| <= c n eps32 ||M||; with
+  n <= 256 the relative Frobenius error of R against the FP64 factorisation of
+  the same FP32 matrix is held to 2e-5 (rows normalised to a positive
+  diagonal, since the reflector sign convention fixes R only up to row signs
+  where a pivot is zero).
+  Inverse: column-wise back substitution has forward error about
+  kappa(R) * n * eps32; the test matrices have kappa(R) < 100, bound 2e-4.
+  Solve: the stopping rule is ||A^T r|| / (||A||_F ||r||) <= 1e-10 in FP64;
+  the oracle recomputes it from the returned x (bound 1.5e-10: the GPU sums
+  A^T r in another order), and ||x - x_opt|| / ||x_opt|| <= 1e-8 against
+  FP64 Householder least squares of the stored A (kappa(A) < 10 here, so the
+  criterion bounds the forward error well below that).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.ls import householder_lstsq, householder_qr, ne_criterion
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2606_20195_amd import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch,  # noqa: E402
+                                  SketchError, qr_f32, trinv_f32)
+
+DEV = "cuda:0"
+NP_DT = {torch.float32: np.float32, torch.float16: np.float16}
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _row_sign_normalise(R):
+    s = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return R * s[:, None]
+
+
+@pytest.mark.parametrize("rows,n", [(256, 32), (1024, 256), (300, 37), (2048, 40), (65, 64), (96, 1),
+                                    (1200, 40), (1200, 300), (500, 50), (4096, 100)])   # panels of 17-31 columns
+def test_qr_matches_fp64(rows, n):
+    M = workloads.gaussian(rows, n + 1, 11 + n, np.float32)
+    Md = torch.from_numpy(M).to(DEV)
+    tau = qr_f32(Md, n)
+    torch.cuda.synchronize()
+    got = _np(Md).astype(np.float64)
+    R_gpu = np.triu(got[:n, :n])
+    _, R_ref = householder_qr(M[:, :n])
+    Rg, Rr = _row_sign_normalise(R_gpu), _row_sign_normalise(R_ref)
+    err = np.linalg.norm(Rg - Rr) / np.linalg.norm(Rr)
+    assert err <= 2e-5, err
+    # the last column holds Q^T m_n: check it through the identity R^T (Q^T c) = M^T c
+    z = got[:n, n] * np.where(np.diag(R_gpu) < 0, -1.0, 1.0)
+    lhs = Rg.T @ z
+    rhs = M[:, :n].astype(np.float64).T @ M[:, n].astype(np.float64)
+    assert np.linalg.norm(lhs - rhs) <= 2e-5 * np.linalg.norm(M[:, :n]) * np.linalg.norm(M[:, n])
+    assert np.all(np.isfinite(_np(tau)))
+
+
+@pytest.mark.parametrize("n", [1, 16, 40, 256, 300])
+def test_trinv_matches_fp64(n):
+    g = workloads.rng(100 + n)
+    R = np.triu(g.standard_normal((n, n)) * 0.1) + np.diag(1.0 + g.random(n))
+    R = R.astype(np.float32)
+    P, PT, bad = trinv_f32(torch.from_numpy(R).to(DEV))
+    torch.cuda.synchronize()
+    P, PT = _np(P).astype(np.float64), _np(PT).astype(np.float64)
+    assert int(_np(bad)[0]) == 0
+    ref = np.linalg.inv(R.astype(np.float64))
+    assert np.linalg.norm(P - ref) <= 2e-4 * np.linalg.norm(ref)
+    assert np.array_equal(P, PT.T)
+    assert np.all(np.tril(P, -1) == 0)
+
+
+def test_trinv_flags_zero_pivot():
+    R = np.triu(np.ones((20, 20), np.float32))
+    R[7, 7] = 0.0
+    _, _, bad = trinv_f32(torch.from_numpy(R).to(DEV))
+    torch.cuda.synchronize()
+    assert int(_np(bad)[0]) == 1
+
+
+def _solve_case(m, n, d, s, rounding, dtype, kind="gaussian", noise=1e-6, seed=7):
+    if kind == "coherent":
+        A = workloads.coherent(m, n, seed, dtype)
+    else:
+        A = workloads.gaussian(m, n, seed, dtype)
+    xs = workloads.rng(seed + 1).standard_normal(n)
+    b = A.astype(np.float64) @ xs + noise * workloads.rng(seed + 2).standard_normal(m)
+    sk = Sketch(m, d, s, 0, rounding)
+    Ad = torch.from_numpy(A).to(DEV)
+    bd = torch.from_numpy(b).to(DEV)
+    x, info = sk.solve(Ad, bd)
+    torch.cuda.synchronize()
+    return A, b, xs, _np(x), info
+
+
+@pytest.mark.parametrize("rounding", [ACC_F32, ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER])
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_solve_small_matches_oracle(rounding, dtype):
+    A, b, _, x, info = _solve_case(16384, 32, 128, 4, rounding, dtype)
+    assert info["converged"] == 1, info
+    x_opt = householder_lstsq(A, b)
+    crit = ne_criterion(A, b, x)
+    assert crit <= 1.5e-10, (crit, info)
+    assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt), info
+    assert info["crit"] <= 1e-10
+    assert abs(info["rel_residual"] - np.linalg.norm(b - A.astype(np.float64) @ x) / np.linalg.norm(b)) <= 1e-9
+
+
+@pytest.mark.parametrize("m,n,d,s,dtype", [(20000, 17, 68, 4, np.float16),   # ragged row chunks, odd n
+                                           (5000, 3, 12, 1, np.float32),      # CountSketch, tiny n
+                                           (65536, 130, 520, 4, np.float16),  # 17 chunks per row
+                                           (30000, 300, 1200, 4, np.float32),  # two chunks per lane
+                                           (20000, 520, 2080, 4, np.float32)])  # four chunks per lane
+def test_solve_shapes(m, n, d, s, dtype):
+    A, b, _, x, info = _solve_case(m, n, d, s, ACC_F16_RN if dtype == np.float16 else ACC_F32, dtype)
+    assert info["converged"] == 1, info
+    assert ne_criterion(A, b, x) <= 1.5e-10
+    x_opt = householder_lstsq(A, b)
+    assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
+
+
+def test_solve_padded_lda_and_bf16():
+    m, n = 12000, 24
+    A = workloads.gaussian(m, n, 21, np.float32)
+    xs = workloads.rng(22).standard_normal(n)
+    b = A.astype(np.float64) @ xs + 1e-6 * workloads.rng(23).standard_normal(m)
+    big = torch.zeros((m, 40), dtype=torch.float32, device=DEV)
+    big[:, :n] = torch.from_numpy(A).to(DEV)
+    big[:, n:] = float("nan")            # padding must never be read into the result
+    sk = Sketch(m, 96, 4, 3, ACC_F32)
+    x, info = sk.solve(big[:, :n], torch.from_numpy(b).to(DEV))
+    assert info["converged"] == 1
+    assert ne_criterion(A, b, _np(x)) <= 1.5e-10
+    # BF16 storage: the solution is the FP64 optimum for the stored BF16 matrix
+    Ab = torch.from_numpy(A).to(DEV).to(torch.bfloat16)
+    A_st = Ab.float().cpu().numpy()
+    x2, info2 = Sketch(m, 96, 4, 3, ACC_F16_RN).solve(Ab, torch.from_numpy(b).to(DEV))
+    assert info2["converged"] == 1
+    x_opt = householder_lstsq(A_st, b)
+    assert np.linalg.norm(_np(x2) - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
+
+
+def test_solve_consistent_system_recovers_x():
+    A, b, xs, x, info = _solve_case(40000, 48, 192, 4, ACC_F16_RN, np.float16, kind="coherent", noise=0.0)
+    assert info["converged"] == 1
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_solve_coherent_fp16_vs_fp32_plain():
+    m, n, d = 1 << 18, 64, 256
+    A16, b, _ = workloads.ls_case(m, n, np.float16)
+    xo = householder_lstsq(A16, b)
+    out = {}
+    for name, Adt, rounding in [("fp16", A16, ACC_F16_RN), ("fp32", A16.astype(np.float32), ACC_F32)]:
+        sk = Sketch(m, d, 4, 0, rounding)
+        x, info = sk.solve(torch.from_numpy(Adt).to(DEV), torch.from_numpy(b).to(DEV))
+        x = _np(x)
+        assert info["converged"] == 1, (name, info)
+        assert ne_criterion(A16, b, x) <= 1.5e-10
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+        out[name] = x
+    # both storages hold the same values, so both converge to the same optimum
+    assert np.linalg.norm(out["fp16"] - out["fp32"]) <= 2e-8 * np.linalg.norm(xo)
+
+
+def test_solve_epochs_and_repeat_give_same_answer():
+    m, n, d = 50000, 40, 160
+    A = workloads.gaussian(m, n, 31, np.float16)
+    b = A.astype(np.float64) @ workloads.rng(32).standard_normal(n) + 1e-6 * workloads.rng(33).standard_normal(m)
+    sk = Sketch(m, d, 4, 9, ACC_F16_SR)
+    Ad, bd = torch.from_numpy(A).to(DEV), torch.from_numpy(b).to(DEV)
+    xs = []
+    for ep in range(3):
+        x, info = sk.solve(Ad, bd, epoch=ep)
+        assert info["converged"] == 1
+        xs.append(_np(x))
+    for x in xs[1:]:
+        assert np.linalg.norm(x - xs[0]) <= 1e-9 * np.linalg.norm(xs[0])
+
+
+def test_solve_rank_deficient_and_notconv():
+    m, n = 8192, 16
+    A = workloads.gaussian(m, n, 41, np.float32)
+    A[:, 5] = 0.0
+    b = workloads.rng(42).standard_normal(m)
+    sk = Sketch(m, 64, 4, 0, ACC_F32)
+    with pytest.raises(SketchError) as ei:
+        sk.solve(torch.from_numpy(A).to(DEV), torch.from_numpy(b).to(DEV))
+    assert ei.value.code == -1 and "rank" in str(ei.value)
+    A[:, 5] = workloads.rng(43).standard_normal(m)
+    Ad, bd = torch.from_numpy(A).to(DEV), torch.from_numpy(b).to(DEV)
+    x, info = sk.solve(Ad, bd, tol=1e-300, max_refine=1, raise_on_notconv=False)
+    assert info["converged"] == 0 and info["refine_steps"] == 1
+    assert info["crit"] == pytest.approx(ne_criterion(A, b, _np(x)), rel=1e-3, abs=1e-14)
+    with pytest.raises(SketchError) as ei:
+        sk.solve(Ad, bd, tol=1e-300, max_refine=1)
+    assert ei.value.code == -5
+
+
+def test_solve_full_size_coherent_fp16():
+    """A 2097152 x 256 coherent FP16, d = 1024, s = 4, FP16-RN sketch: the
+    oracle recomputes the stopping criterion in FP64 from the returned x, and
+    compares x with its FP64 Householder solution."""
+    from oracle import native
+    A, b, _ = workloads.ls_case()
+    m, n = A.shape
+    sk = Sketch(m, 1024, 4, 0, ACC_F16_RN)
+    Ad, bd = torch.from_numpy(A).to(DEV), torch.from_numpy(b).to(DEV)
+    x, info = sk.solve(Ad, bd)
+    x = _np(x)
+    print("full-size solve:", info, flush=True)
+    assert info["converged"] == 1
+    del Ad
+    # criterion in FP64, in row blocks
+    g = np.zeros(n)
+    rr = 0.0
+    fro = 0.0
+    for r0 in range(0, m, 1 << 18):
+        Ab = A[r0:r0 + (1 << 18)].astype(np.float64)
+        r = b[r0:r0 + (1 << 18)] - Ab @ x
+        g += Ab.T @ r
+        rr += r @ r
+        fro += np.sum(Ab * Ab)
+    crit = np.linalg.norm(g) / (np.sqrt(fro) * np.sqrt(rr))
+    assert crit <= 1.5e-10, crit
+    x_opt = native.lstsq(A, b)
+    assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
