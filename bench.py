@@ -9,8 +9,16 @@ A, hash, scale, quantise, accumulate) with A already resident in HBM.
 Printed: one JSON line with the effective HBM bandwidth (algorithmic bytes
 m*n*2 + d*n*2 per step over the step time), the roofline record of the
 dominant kernel (apply kernel time from HIP events on the stream the library
-launches on), the same figure for the other accumulation modes, and the FP64
-CPU oracle timed on a bounded sample of the same input.
+launches on), the same figure for the other accumulation modes, the
+least-squares leg (sketch_solve on a 2097152 x 256 coherent problem, FP16
+storage with an FP16-RN sketch against the FP32 plain path: solves/s and
+p50/p99 latency to the 1e-10 normal-equations criterion), and the FP64 CPU
+oracle timed on a bounded sample of the same input.
+
+--profile-run replaces all of that by a short fixed sequence for rocprofv3
+counter passes: three 512 MiB device copies (the calibration of FETCH_SIZE
+and WRITE_SIZE against a known byte count) and three accumulate-mode calls of
+the headline apply (one apply kernel launch each).
 """
 from __future__ import annotations
 
@@ -40,6 +48,9 @@ def parse():
     p.add_argument("--modes", default="f32,sr,dither,a32",
                    help="extra runs to time: f32/sr/dither accumulation on the FP16 input, a32 = FP32-stored "
                         "input with FP32 accumulation; empty = the headline run only")
+    p.add_argument("--ls-solves", type=int, default=30, help="timed solves per path in the least-squares leg "
+                   "(0 = skip the leg)")
+    p.add_argument("--profile-run", action="store_true", help="short fixed sequence for counter passes")
     return p.parse_args()
 
 
@@ -99,6 +110,69 @@ def cpu_baseline():
                       "per-thread partials" % (rows, reps)}
 
 
+def ls_leg(nsolves, stream):
+    """sketch_solve on the 2097152 x 256 coherent problem (d = 1024, s = 4):
+    FP16 storage + FP16-RN sketch against FP32 storage + FP32 sketch."""
+    import torch
+    import workloads
+    from paper_2606_20195_amd import ACC_F16_RN, ACC_F32, Sketch
+    A16, b, _ = workloads.ls_case()
+    m, n = A16.shape
+    d = workloads.LSQ["d"]
+    bd = torch.from_numpy(b).cuda()
+    out = {"workload": "least squares A %dx%d coherent (1e-3 N(0,1), rows 0..%d = 100 I), d=%d, s=4, "
+                       "b = A x* + 1e-6 N(0,1); stop at ||A^T r||/(||A||_F ||r||) <= 1e-10" % (m, n, n - 1, d)}
+    for name, rounding, dt in (("fp16", ACC_F16_RN, torch.float16), ("fp32_plain", ACC_F32, torch.float32)):
+        Ad = torch.from_numpy(A16).cuda().to(dt)
+        sk = Sketch(m, d, 4, 0, rounding)
+        x, info = sk.solve(Ad, bd, epoch=0)           # warm-up: workspace, code objects
+        times, infos = [], []
+        for k in range(nsolves):
+            t0 = time.perf_counter()
+            x, info = sk.solve(Ad, bd, epoch=k + 1)    # returns after the device finished
+            times.append((time.perf_counter() - t0) * 1e3)
+            infos.append(info)
+        times = np.array(times)
+        out[name] = {
+            "solves_per_s": round(1e3 / float(times.mean()), 2),
+            "p50_ms": round(float(np.percentile(times, 50)), 3),
+            "p99_ms": round(float(np.percentile(times, 99)), 3),
+            "converged": int(sum(i["converged"] for i in infos)), "solves": nsolves,
+            "refine_steps": float(np.mean([i["refine_steps"] for i in infos])),
+            "inner_iters": float(np.mean([i["inner_iters"] for i in infos])),
+            "crit_max": float(max(i["crit"] for i in infos)),
+            "rel_residual": float(np.mean([i["rel_residual"] for i in infos])),
+            "rel_residual_x0": float(np.mean([i["rel_residual_x0"] for i in infos])),
+            "ms_sketch": round(float(np.mean([i["ms_sketch"] for i in infos])), 3),
+            "ms_factor": round(float(np.mean([i["ms_factor"] for i in infos])), 3),
+            "ms_refine": round(float(np.mean([i["ms_refine"] for i in infos])), 3),
+        }
+        del Ad, sk
+        torch.cuda.empty_cache()
+    out["fp16_speedup"] = round(out["fp16"]["solves_per_s"] / out["fp32_plain"]["solves_per_s"], 3)
+    return out
+
+
+def profile_run():
+    """Fixed short sequence for rocprofv3 counter passes."""
+    import torch
+    import workloads
+    from paper_2606_20195_amd import ACC_F16_RN, Sketch
+    src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    A = torch.from_numpy(workloads.apply_case("gaussian", dtype=np.float16)).cuda()
+    sk = Sketch(M, D, S, 0, ACC_F16_RN)
+    SA = sk.apply(A)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    for _ in range(3):
+        sk.apply(A, SA=SA, accumulate=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "3 copies of %d bytes, 3 apply kernels" % src.numel()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -110,6 +184,9 @@ def main():
     import workloads
     from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
 
+    if args.profile_run:
+        profile_run()
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     A = torch.from_numpy(workloads.apply_case("gaussian", dtype=np.float16)).to(dev)
@@ -157,6 +234,9 @@ def main():
                                   "GB/s": round((M * N * 4 + D * N * 4) / (k32 * 1e-3) / 1e9, 1)}
         del A32
 
+    del A
+    torch.cuda.empty_cache()
+    ls = ls_leg(args.ls_solves, stream) if args.ls_solves > 0 else None
     traffic = measured_traffic()
     line = {
         "metric": "sketch_apply HBM GB/s (% of peak) + LS solves/s, p50/p99 at 1e-10 residual, FP16 vs FP32",
@@ -182,6 +262,8 @@ def main():
                      "algorithmic_bytes": alg_bytes},
         "modes": modes,
     }
+    if ls is not None:
+        line["ls"] = ls
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

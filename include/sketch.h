@@ -154,6 +154,101 @@ int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t *buckets,
 int sketch_quantize(int32_t mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
                     uint32_t epoch, uint64_t site0, void *stream);
 
+/* ---- batches of independent sketches -------------------------------------- */
+
+/*
+ * One problem of a batch: SA = S A with S described by (m, d, s, seed) as in
+ * sketch_create and rounding rule `rounding`; A, SA as in sketch_apply (rows =
+ * m, row_offset = 0, no SK_ACCUMULATE).  All problems of a batch share a_dtype
+ * and the accumulation class (all SK_ACC_F32, or all FP16 rules); m, n, d, s,
+ * seed, rule and epoch may differ.  SA of distinct problems must not overlap.
+ */
+typedef struct sk_problem {
+    int64_t m, n, d;
+    int32_t s, rounding;
+    uint64_t seed;
+    const void *A;
+    int64_t lda;
+    void *SA;
+    int64_t ldsa;
+    int32_t a_dtype;
+    uint32_t round_epoch;
+    int32_t reserved[4];  /* must be zero */
+} sk_problem;
+
+typedef struct sk_batch *sk_batch_handle;
+
+/*
+ * sketch_batch_create -- plan a batch once: validates every problem, picks
+ * the schedule (`sched`, else the tuning table entry for this batch's
+ * signature, else the default), sorts the problems largest first and uploads
+ * their descriptors to the current device.  The problems' A and SA pointers
+ * are recorded and must stay valid while the handle is used.  sched fields:
+ * chunk_rows (rows per work item), block_group, waves; xcd_remap is ignored.
+ * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP.
+ */
+int sketch_batch_create(const sk_problem *probs, int32_t count, const sk_schedule *sched, sk_batch_handle *out);
+
+/*
+ * sketch_batch_apply -- run the batch on `stream`: one kernel clears every
+ * SA and resets the work counter, then ONE persistent launch sketches all
+ * problems, each workgroup taking (problem, unit, column tile) work items
+ * from a device counter (plus one scale kernel for FP32 problems whose
+ * 1/sqrt(s) is not a power of two).  Asynchronous; no allocation, no host
+ * synchronisation, no memset nodes, so it may be captured in a graph.  Calls
+ * on one handle must not overlap (they share the work counter).
+ * Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_batch_apply(sk_batch_handle b, void *stream);
+
+/*
+ * sketch_batch_graph -- the same work replayed from a HIP graph: the first
+ * call captures sketch_batch_apply on a library-owned stream and
+ * instantiates it; every call launches the instantiated graph on `stream`.
+ * Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_batch_graph(sk_batch_handle b, void *stream);
+
+/*
+ * sketch_apply_batched -- one-shot form: create, apply, wait for the stream,
+ * destroy.  Allocates and synchronises; use the handle API for repeated or
+ * captured launches.  Errors: as sketch_batch_create / sketch_batch_apply.
+ */
+int sketch_apply_batched(const sk_problem *probs, int32_t count, const sk_schedule *sched, void *stream);
+
+/* sketch_batch_schedule -- the schedule the batch was planned with. */
+int sketch_batch_schedule(sk_batch_handle b, sk_schedule *out);
+
+/* sketch_batch_destroy -- free descriptors and graph (NULL is accepted). */
+int sketch_batch_destroy(sk_batch_handle b);
+
+/*
+ * sketch_tune_batch -- time candidate schedules (rows per work item x waves
+ * per workgroup) on this batch with real launches (each problem's SA is
+ * overwritten), keep the fastest in the process-wide tuning table under the
+ * batch's signature, append it to the JSON file `cache_path` (NULL: no file)
+ * and return it in *out (may be NULL).  Errors: as sketch_batch_create.
+ */
+int sketch_tune_batch(const sk_problem *probs, int32_t count, const char *cache_path, sk_schedule *out);
+
+/*
+ * sketch_tune_apply -- the same for single sketch_apply calls of this handle
+ * on (a_dtype, rows, n): candidates over chunk_rows x waves x block_group;
+ * SA is overwritten.  The winner is used by later sketch_apply calls with the
+ * same signature (handle's d, s, rounding; a_dtype; n; rows rounded to a
+ * power of two) unless a schedule is forced.  Errors: as sketch_apply.
+ */
+int sketch_tune_apply(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
+                      void *SA, int64_t ldsa, const char *cache_path, sk_schedule *out, void *stream);
+
+/*
+ * sketch_load_tuning -- merge a JSON file written by the tuners into the
+ * tuning table.  Returns the number of entries read (>= 0) or SK_EINVAL (file
+ * missing or malformed).  sketch_clear_tuning empties the table.
+ */
+int sketch_load_tuning(const char *path);
+int sketch_clear_tuning(void);
+
 /* ---- least squares -------------------------------------------------------- */
 
 /*

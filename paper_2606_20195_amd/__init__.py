@@ -13,9 +13,10 @@ from __future__ import annotations
 import ctypes
 
 from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, ENOTCONV, F16, F32,
-                   Schedule, SketchError, SolveInfo, SolveOpts, check, load)
+                   Problem, Schedule, SketchError, SolveInfo, SolveOpts, check, load)
 
-__all__ = ["Sketch", "SketchError", "Schedule", "quantize", "qr_f32", "trinv_f32", "version", "ACC_F32",
+__all__ = ["Sketch", "SketchError", "Schedule", "Batch", "tune_batch", "load_tuning", "clear_tuning", "quantize",
+           "qr_f32", "trinv_f32", "version", "ACC_F32",
            "ACC_F16_RN",
            "ACC_F16_SR", "ACC_F16_DITHER", "F32", "F16", "BF16", "ACCUMULATE"]
 
@@ -129,6 +130,20 @@ class Sketch:
             check(rc, "sketch_solve")
         return x, info.as_dict()
 
+    def tune(self, A, SA=None, cache_path=None, stream=None):
+        """Time candidate schedules for sketch_apply on A (SA is overwritten);
+        the winner is used by later calls with the same signature."""
+        lda = _matrix(A, "A")
+        rows, n = A.shape
+        if SA is None:
+            SA = self.empty_output(n, A.device)
+        sch = Schedule()
+        check(self._lib.sketch_tune_apply(self._h, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), rows, n, lda,
+                                          ctypes.c_void_p(SA.data_ptr()), _matrix(SA, "SA"),
+                                          cache_path.encode() if cache_path else None, ctypes.byref(sch),
+                                          _stream(stream)), "sketch_tune_apply")
+        return sch.as_dict()
+
     def set_schedule(self, chunk_rows=0, block_group=0, waves=0, xcd_remap=1):
         sch = Schedule(chunk_rows, block_group, waves, xcd_remap)
         check(self._lib.sketch_set_schedule(self._h, ctypes.byref(sch)), "sketch_set_schedule")
@@ -149,6 +164,74 @@ class Sketch:
         check(self._lib.sketch_hash(self._h, int(row_begin), int(count), ctypes.c_void_p(b.data_ptr()),
                                     ctypes.c_void_p(g.data_ptr()), _stream(stream)), "sketch_hash")
         return b, g
+
+
+def _problems(specs):
+    """specs: dicts with m (optional: A.shape[0]), d, s, seed, rounding, A, SA, epoch."""
+    arr = (Problem * len(specs))()
+    for i, sp in enumerate(specs):
+        A, SA = sp["A"], sp["SA"]
+        m, n = A.shape
+        arr[i] = Problem(m, n, int(sp["d"]), int(sp["s"]), int(sp.get("rounding", ACC_F16_RN)),
+                         int(sp.get("seed", 0)) & (2 ** 64 - 1), A.data_ptr(), _matrix(A, "A"), SA.data_ptr(),
+                         _matrix(SA, "SA"), _dtype_code(A), int(sp.get("epoch", 0)) & 0xFFFFFFFF)
+    return arr
+
+
+class Batch:
+    """Many independent sketches run by one persistent launch (optionally a
+    replayed HIP graph).  The tensors in `specs` must outlive the batch."""
+
+    def __init__(self, specs, chunk_rows=0, block_group=0, waves=0):
+        self._lib = load()
+        self._specs = list(specs)
+        arr = _problems(self._specs)
+        sch = Schedule(chunk_rows, block_group, waves, 0)
+        use = ctypes.byref(sch) if (chunk_rows or block_group or waves) else None
+        h = ctypes.c_void_p()
+        check(self._lib.sketch_batch_create(arr, len(arr), use, ctypes.byref(h)), "sketch_batch_create")
+        self._h = h
+
+    def apply(self, stream=None):
+        check(self._lib.sketch_batch_apply(self._h, _stream(stream)), "sketch_batch_apply")
+
+    def graph(self, stream=None):
+        check(self._lib.sketch_batch_graph(self._h, _stream(stream)), "sketch_batch_graph")
+
+    def schedule(self):
+        sch = Schedule()
+        check(self._lib.sketch_batch_schedule(self._h, ctypes.byref(sch)), "sketch_batch_schedule")
+        return sch.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sketch_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_batch(specs, cache_path=None):
+    arr = _problems(specs)
+    sch = Schedule()
+    check(load().sketch_tune_batch(arr, len(arr), cache_path.encode() if cache_path else None, ctypes.byref(sch)),
+          "sketch_tune_batch")
+    return sch.as_dict()
+
+
+def load_tuning(path):
+    rc = load().sketch_load_tuning(str(path).encode())
+    if rc < 0:
+        check(rc, "sketch_load_tuning")
+    return rc
+
+
+def clear_tuning():
+    check(load().sketch_clear_tuning(), "sketch_clear_tuning")
 
 
 def qr_f32(M, k, stream=None):

@@ -21,7 +21,9 @@ ACCUMULATE = 1
 
 EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedule", "sketch_plan",
            "sketch_hash", "sketch_quantize", "sketch_solve", "sketch_qr_f32", "sketch_trinv_f32",
-           "sketch_last_error", "sketch_version")
+           "sketch_batch_create", "sketch_batch_apply", "sketch_batch_graph", "sketch_batch_schedule",
+           "sketch_batch_destroy", "sketch_apply_batched", "sketch_tune_batch", "sketch_tune_apply",
+           "sketch_load_tuning", "sketch_clear_tuning", "sketch_last_error", "sketch_version")
 
 
 class Schedule(ctypes.Structure):
@@ -32,6 +34,13 @@ class Schedule(ctypes.Structure):
     def as_dict(self):
         return dict(chunk_rows=self.chunk_rows, block_group=self.block_group, waves=self.waves,
                     xcd_remap=self.xcd_remap)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("s", ctypes.c_int32),
+                ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint64), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("SA", ctypes.c_void_p), ("ldsa", ctypes.c_int64),
+                ("a_dtype", ctypes.c_int32), ("round_epoch", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -80,6 +89,19 @@ def load():
                          ctypes.c_int),
         "sketch_qr_f32": ([P, i64, i64, i64, i64, P, P], ctypes.c_int),
         "sketch_trinv_f32": ([P, i64, i64, P, P, i64, P, P], ctypes.c_int),
+        "sketch_batch_create": ([ctypes.POINTER(Problem), i32, ctypes.POINTER(Schedule), ctypes.POINTER(P)],
+                                ctypes.c_int),
+        "sketch_batch_apply": ([P, P], ctypes.c_int),
+        "sketch_batch_graph": ([P, P], ctypes.c_int),
+        "sketch_batch_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "sketch_batch_destroy": ([P], ctypes.c_int),
+        "sketch_apply_batched": ([ctypes.POINTER(Problem), i32, ctypes.POINTER(Schedule), P], ctypes.c_int),
+        "sketch_tune_batch": ([ctypes.POINTER(Problem), i32, ctypes.c_char_p, ctypes.POINTER(Schedule)],
+                              ctypes.c_int),
+        "sketch_tune_apply": ([P, P, i32, i64, i64, i64, P, i64, ctypes.c_char_p, ctypes.POINTER(Schedule), P],
+                              ctypes.c_int),
+        "sketch_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
+        "sketch_clear_tuning": ([], ctypes.c_int),
         "sketch_last_error": ([], ctypes.c_char_p),
         "sketch_version": ([], ctypes.c_int),
     }

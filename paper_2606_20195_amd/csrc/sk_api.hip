@@ -64,6 +64,19 @@ int apply_max_waves(int32_t a_dtype);
 int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo& dev,
               Plan* out)
 {
+    if (!h->forced) {
+        // a tuned schedule for this signature, if one is known and valid here
+        sk_sketch tuned = *h;
+        if (tuning_lookup(apply_key(h, a_dtype, rows, n), &tuned.sched)) {
+            tuned.forced = true;
+            Plan pl;
+            if (make_plan(&tuned, a_dtype, rows, n, lda, dev, &pl) == SK_OK) {
+                *out = pl;
+                return SK_OK;
+            }
+            set_error(SK_OK, "");
+        }
+    }
     const int64_t W = h->d / h->s;
     const sk_schedule* f = h->forced ? &h->sched : nullptr;
     const bool dual = h->rounding == SK_ACC_F32;   // FP32 mode keeps two fields per element

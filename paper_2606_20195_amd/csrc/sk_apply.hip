@@ -252,28 +252,15 @@ __device__ __forceinline__ int binade_of(uint32_t magbits)
 // modes), 2 = two fields per element (FP32 mode): the rounded value and its
 // residual at 2^-21 finer resolution, kept in two LDS arrays with the same
 // layout, so each unit is summed with about 41 significant bits.
+// One work item: the partial sketch of unit `unit` (rows [unit * chunk_rows,
+// ...)), column tile `ct` and block group `bgi`, accumulated in LDS and added
+// into SA.  Called by every thread of the workgroup; ends with LDS free.
 template <typename AT, int BG, bool VEC, int ACC>
-__global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
+__device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct, int bgi, float* lds)
 {
-    extern __shared__ float lds[];
     const int nwaves = (int)(blockDim.x >> 6);
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
-
-    const int per_unit = p.col_tiles * p.bgroups;
-    int unit, t;
-    if (p.xcd_remap) {
-        // Consecutive workgroup ids go to different XCDs; give all tiles of a
-        // unit the same id modulo 8 so they read the unit's rows through one L2.
-        const int x = (int)(blockIdx.x & 7u), sidx = (int)(blockIdx.x >> 3);
-        unit = (sidx / per_unit) * 8 + x;
-        t = sidx % per_unit;
-    } else {
-        unit = (int)blockIdx.x / per_unit;
-        t = (int)blockIdx.x % per_unit;
-    }
-    const int ct = t % p.col_tiles;
-    const int bgi = t / p.col_tiles;
     const int64_t r_begin = (int64_t)unit * p.chunk_rows;
     const int64_t r_end = min(r_begin + (int64_t)p.chunk_rows, p.rows);
     const int c0 = ct * kNT;
@@ -619,6 +606,91 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
     }
 }
 
+template <typename AT, int BG, bool VEC, int ACC>
+__global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
+{
+    extern __shared__ float lds[];
+    const int per_unit = p.col_tiles * p.bgroups;
+    int unit, t;
+    if (p.xcd_remap) {
+        // Consecutive workgroup ids go to different XCDs; give all tiles of a
+        // unit the same id modulo 8 so they read the unit's rows through one L2.
+        const int x = (int)(blockIdx.x & 7u), sidx = (int)(blockIdx.x >> 3);
+        unit = (sidx / per_unit) * 8 + x;
+        t = sidx % per_unit;
+    } else {
+        unit = (int)blockIdx.x / per_unit;
+        t = (int)blockIdx.x % per_unit;
+    }
+    apply_item<AT, BG, VEC, ACC>(p, unit, t % p.col_tiles, t / p.col_tiles, lds);
+}
+
+// Persistent form for many problems: each workgroup takes work items from a
+// device counter until the batch's items run out.  descs[] is sorted so the
+// largest problems' items come first; item0 is a problem's first flat item.
+template <typename AT, int BG, bool VEC, int ACC>
+__global__ __launch_bounds__(kMaxThreads<AT>) void apply_batched_kernel(const BatchDesc* descs, int32_t count,
+                                                                         int64_t total_items, uint32_t* counter)
+{
+    extern __shared__ float lds[];
+    __shared__ int64_t s_item;
+    __shared__ int32_t s_prob;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t it = (int64_t)atomicAdd(counter, 1u);
+            int lo = 0, hi = count - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (descs[mid].item0 <= it) lo = mid;
+                else hi = mid - 1;
+            }
+            s_item = it;
+            s_prob = lo;
+        }
+        __syncthreads();
+        const int64_t it = s_item;
+        const int pi = __builtin_amdgcn_readfirstlane(s_prob);
+        if (it >= total_items) break;
+        const BatchDesc* bd = descs + pi;
+        const int local = __builtin_amdgcn_readfirstlane((int)(it - bd->item0));
+        const int per_unit = bd->a.col_tiles * bd->a.bgroups;
+        const int t = local % per_unit;
+        apply_item<AT, BG, VEC, ACC>(bd->a, local / per_unit, t % bd->a.col_tiles, t / bd->a.col_tiles, lds);
+        __syncthreads();
+    }
+}
+
+// Clears every problem's SA (and resets the work counter) before a batched apply.
+__global__ void batch_fill_kernel(const BatchDesc* descs, int32_t count, uint32_t* counter)
+{
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0u;
+    const int pi = (int)blockIdx.y;
+    if (pi >= count) return;
+    const ApplyArgs& a = descs[pi].a;
+    const int64_t total = (int64_t)a.d * a.n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / a.n, c = e - r * a.n;
+        if (a.mode == 0) ((float*)a.SA)[r * a.ldsa + c] = 0.0f;
+        else ((uint16_t*)a.SA)[r * a.ldsa + c] = 0;
+    }
+}
+
+// FP32 problems whose 1/sqrt(s) is not a power of two: SA = fl32(c_s * SA).
+__global__ void batch_scale_kernel(const BatchDesc* descs, int32_t count)
+{
+    const int pi = (int)blockIdx.y;
+    if (pi >= count) return;
+    const BatchDesc& bd = descs[pi];
+    if (bd.post_scale == 0.0f) return;
+    const ApplyArgs& a = bd.a;
+    const int64_t total = (int64_t)a.d * a.n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / a.n, c = e - r * a.n;
+        float* dst = (float*)a.SA + r * a.ldsa + c;
+        *dst = bd.post_scale * *dst;
+    }
+}
+
 __global__ void fill_kernel(void* p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld)
 {
     const int64_t total = rows * cols;
@@ -715,6 +787,49 @@ hipError_t launch_vec(const Plan& plan, const ApplyArgs& a, hipStream_t st)
     return a.aligned ? launch_bg<AT, true>(plan, a, st) : launch_bg<AT, false>(plan, a, st);
 }
 
+// grid == 0: only raise the kernel's dynamic-LDS limit (done before a graph capture).
+template <typename AT, int BG, bool VEC, int ACC>
+hipError_t launch_batched_kernel(const BatchDesc* descs, int32_t count, int64_t total_items, uint32_t* counter,
+                                 int grid, int waves, size_t lds_bytes, hipStream_t st)
+{
+    static size_t attr_bytes = 0;
+    auto kern = apply_batched_kernel<AT, BG, VEC, ACC>;
+    if (lds_bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        attr_bytes = lds_bytes;
+    }
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((unsigned)(64 * waves)), lds_bytes, st, descs, count,
+                       total_items, counter);
+    return hipGetLastError();
+}
+
+template <typename AT, bool VEC, int ACC>
+hipError_t batched_bg(int bg, const BatchDesc* descs, int32_t count, int64_t total_items, uint32_t* counter,
+                      int grid, int waves, size_t lds_bytes, hipStream_t st)
+{
+    switch (bg) {
+    case 1: return launch_batched_kernel<AT, 1, VEC, ACC>(descs, count, total_items, counter, grid, waves, lds_bytes, st);
+    case 2: return launch_batched_kernel<AT, 2, VEC, ACC>(descs, count, total_items, counter, grid, waves, lds_bytes, st);
+    case 4: return launch_batched_kernel<AT, 4, VEC, ACC>(descs, count, total_items, counter, grid, waves, lds_bytes, st);
+    case 8: return launch_batched_kernel<AT, 8, VEC, ACC>(descs, count, total_items, counter, grid, waves, lds_bytes, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename AT>
+hipError_t batched_typed(int bg, bool vec, bool dual, const BatchDesc* descs, int32_t count, int64_t total_items,
+                         uint32_t* counter, int grid, int waves, size_t lds_bytes, hipStream_t st)
+{
+    if (dual)
+        return vec ? batched_bg<AT, true, 2>(bg, descs, count, total_items, counter, grid, waves, lds_bytes, st)
+                   : batched_bg<AT, false, 2>(bg, descs, count, total_items, counter, grid, waves, lds_bytes, st);
+    return vec ? batched_bg<AT, true, 1>(bg, descs, count, total_items, counter, grid, waves, lds_bytes, st)
+               : batched_bg<AT, false, 1>(bg, descs, count, total_items, counter, grid, waves, lds_bytes, st);
+}
+
 unsigned grid_for(int64_t work, int threads)
 {
     int64_t g = (work + threads - 1) / threads;
@@ -752,6 +867,35 @@ hipError_t launch_apply(int a_dtype, const Plan& plan, const ApplyArgs& a, hipSt
     case SK_BF16: return launch_vec<__hip_bfloat16>(plan, a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t prepare_batched(int a_dtype, int bg, bool vec, bool dual, size_t lds_bytes)
+{
+    switch (a_dtype) {
+    case SK_F32: return batched_typed<float>(bg, vec, dual, nullptr, 0, 0, nullptr, 0, 8, lds_bytes, nullptr);
+    case SK_F16: return batched_typed<__half>(bg, vec, dual, nullptr, 0, 0, nullptr, 0, 8, lds_bytes, nullptr);
+    case SK_BF16: return batched_typed<__hip_bfloat16>(bg, vec, dual, nullptr, 0, 0, nullptr, 0, 8, lds_bytes, nullptr);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchDesc* descs, int32_t count,
+                          int64_t total_items, uint32_t* counter, int grid, int waves, size_t lds_bytes,
+                          bool post_scale, int64_t max_dn, hipStream_t st)
+{
+    const unsigned fx = grid_for(max_dn, 256) < 64u ? grid_for(max_dn, 256) : 64u;
+    hipLaunchKernelGGL(batch_fill_kernel, dim3(fx, (unsigned)count), dim3(256), 0, st, descs, count, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (a_dtype) {
+    case SK_F32: e = batched_typed<float>(bg, vec, dual, descs, count, total_items, counter, grid, waves, lds_bytes, st); break;
+    case SK_F16: e = batched_typed<__half>(bg, vec, dual, descs, count, total_items, counter, grid, waves, lds_bytes, st); break;
+    case SK_BF16: e = batched_typed<__hip_bfloat16>(bg, vec, dual, descs, count, total_items, counter, grid, waves, lds_bytes, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || !post_scale) return e;
+    hipLaunchKernelGGL(batch_scale_kernel, dim3(fx, (unsigned)count), dim3(256), 0, st, descs, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(void* p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld, hipStream_t st)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <algorithm>
+#include <string>
 
 #include "../../include/sketch.h"
 
@@ -67,13 +68,31 @@ struct ApplyArgs {
     int32_t aligned;     // vector loads allowed
 };
 
+// One problem of a batched apply.
+struct BatchDesc {
+    ApplyArgs a;
+    int64_t item0;       // first flat work item of this problem
+    float post_scale;    // FP32 mode with a non-power-of-two 1/sqrt(s): c_s, else 0
+    int32_t pad;
+};
+
 hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
+// Clear all SAs, one persistent apply over all problems, FP32 epilogue scale if needed.
+hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count,
+                          int64_t total_items, uint32_t *counter, int grid, int waves, size_t lds_bytes,
+                          bool post_scale, int64_t max_dn, hipStream_t st);
 hipError_t launch_fill(void *p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
 hipError_t launch_scale(float *SA, int64_t d, int64_t n, int64_t ldsa, const float *ws, float c,
                         int accumulate, hipStream_t st);
 hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, int64_t count,
                        int32_t *buckets, int8_t *signs, hipStream_t st);
 void solve_release(sk_sketch *h);
+
+// Tuning table (filled by the autotuners, read by the planners).
+std::string apply_key(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n);
+bool tuning_lookup(const std::string &key, sk_schedule *out);
+// Raise the batched kernel's dynamic-LDS limit without launching.
+hipError_t prepare_batched(int a_dtype, int bg, bool vec, bool dual, size_t lds_bytes);
 
 hipError_t launch_quantize(int mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,
                            uint32_t epoch, uint64_t site0, hipStream_t st);

@@ -151,3 +151,52 @@ def test_qr_trinv_validation(lib):
     assert lib.sketch_trinv_f32(FAKE, 2000, 2000, FAKE, FAKE, 2000, FAKE, None) == _lib.EINVAL
     assert lib.sketch_trinv_f32(FAKE, 8, 7, FAKE, FAKE, 8, FAKE, None) == _lib.EINVAL
     assert lib.sketch_trinv_f32(FAKE, 8, 8, FAKE, None, 8, FAKE, None) == _lib.EINVAL
+
+
+def _problem(**kw):
+    P = _lib.Problem
+    base = dict(m=1000, n=8, d=32, s=4, rounding=1, seed=0, A=0x10000, lda=8, SA=0x20000, ldsa=8, a_dtype=1)
+    base.update(kw)
+    return P(base["m"], base["n"], base["d"], base["s"], base["rounding"], base["seed"], base["A"], base["lda"],
+             base["SA"], base["ldsa"], base["a_dtype"], 0)
+
+
+def test_batch_validation(lib):
+    h = ctypes.c_void_p()
+    arr = lambda *ps: (_lib.Problem * len(ps))(*ps)   # noqa: E731
+    mk = lambda *ps: lib.sketch_batch_create(arr(*ps), len(ps), None, ctypes.byref(h))   # noqa: E731
+    assert lib.sketch_batch_create(None, 0, None, ctypes.byref(h)) == _lib.EINVAL
+    assert mk(_problem(m=0)) == _lib.EINVAL
+    assert mk(_problem(d=30)) == _lib.EINVAL                                 # d % s
+    assert mk(_problem(s=17)) == _lib.EINVAL
+    assert mk(_problem(rounding=9)) == _lib.EINVAL
+    assert mk(_problem(A=0)) == _lib.EINVAL
+    assert mk(_problem(lda=4)) == _lib.EINVAL
+    assert mk(_problem(ldsa=9)) == _lib.EUNSUPPORTED                         # FP16 SA needs even ldsa
+    assert mk(_problem(), _problem(a_dtype=0)) == _lib.EINVAL                # mixed element types
+    assert mk(_problem(), _problem(rounding=0)) == _lib.EINVAL               # mixed accumulation classes
+    bad = _problem()
+    bad.reserved[0] = 1
+    assert mk(bad) == _lib.EINVAL
+    S = _lib.Schedule
+    assert lib.sketch_batch_create(arr(_problem()), 1, ctypes.byref(S(100, 0, 0, 0)), ctypes.byref(h)) == _lib.EINVAL
+    assert lib.sketch_batch_destroy(None) == 0
+    assert lib.sketch_batch_apply(None, None) == _lib.EINVAL
+    assert lib.sketch_batch_graph(None, None) == _lib.EINVAL
+
+
+def test_tuning_file_roundtrip(lib, tmp_path):
+    lib.sketch_clear_tuning()
+    good = tmp_path / "tune.json"
+    good.write_text('{"version": 1, "entries": [\n'
+                    ' {"key": "apply a=1 r=1 d=1024 s=4 n=64 rows=2^22", "chunk_rows": 4096, "block_group": 4,'
+                    ' "waves": 8, "xcd_remap": 1, "ms": 0.2},\n'
+                    ' {"key": "batch a=1 acc=f16 k=512 bytes=2^33 nmax=128", "chunk_rows": 8192, "block_group": 4,'
+                    ' "waves": 16, "xcd_remap": 0, "ms": 1.5}]}\n')
+    assert lib.sketch_load_tuning(str(good).encode()) == 2
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"version": 1, "entries": [{"chunk_rows": 1}]}')       # entry without a key
+    assert lib.sketch_load_tuning(str(bad).encode()) == _lib.EINVAL
+    assert lib.sketch_load_tuning(str(tmp_path / "missing.json").encode()) == _lib.EINVAL
+    assert lib.sketch_load_tuning(None) == _lib.EINVAL
+    assert lib.sketch_clear_tuning() == 0
