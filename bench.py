@@ -54,12 +54,15 @@ def parse():
     return p.parse_args()
 
 
+APPLY_SOURCES = ("sk_apply.hip", "sk_device.hpp", "sk_internal.hpp")
+
+
 def kernel_source_digest():
+    """Digest of the sources the apply kernel is built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_20195_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in APPLY_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
