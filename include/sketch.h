@@ -42,6 +42,8 @@ extern "C" {
 #define SK_ENOMEM       -3   /* device allocation failed                      */
 #define SK_EHIP         -4   /* a HIP runtime call failed                     */
 #define SK_ENOTCONV     -5   /* sketch_solve: stopping test not reached       */
+#define SK_EADMIT       -6   /* request larger than the server's memory budget */
+#define SK_EBUSY        -7   /* server shutting down                          */
 
 /* ---- element types ----------------------------------------------------- */
 #define SK_F32  0
@@ -337,6 +339,100 @@ int sketch_qr_f32(float *M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
  */
 int sketch_trinv_f32(const float *R, int64_t n, int64_t ldr, float *P, float *PT, int64_t ldp, int32_t *bad,
                      void *stream);
+
+/* ---- request server ----------------------------------------------------- */
+
+/*
+ * A least-squares request: min ||A x - b|| with the sketch (m, d, s, seed,
+ * rounding) as in sketch_create and options as in sketch_solve.
+ *   gen = 0  A (device, m x n, a_dtype, lda) and b (device FP64) are given by
+ *            the caller and must stay valid until the request completes.
+ *   gen = 1  the server generates A = N(0,1) at admission (gen = 2: coherent,
+ *            1e-3 N(0,1) with rows 0..n-1 = 100 I_n) in a_dtype from gen_seed,
+ *            x* = N(0,1) and b = A x* + 1e-6 N(0,1) in FP64, inside its own
+ *            memory (A, lda, b are ignored).  The generator is Philox4x32-10
+ *            with Box-Muller; its time is reported as ms_ingest.
+ *   x        device FP64, n values: receives the solution.
+ */
+typedef struct sk_request {
+    int64_t m, n, d;
+    int32_t s, rounding;
+    uint64_t seed;
+    int32_t a_dtype, gen;
+    const void *A;
+    int64_t lda;
+    const double *b;
+    double *x;
+    uint64_t gen_seed;
+    sk_solve_opts opts;
+    int32_t reserved[4];  /* must be zero */
+} sk_request;
+
+/* Outcome of one request; times in seconds on the server's clock (sk_server_clock). */
+typedef struct sk_result {
+    int32_t status;       /* SK_OK, SK_ENOTCONV or the error of the solve       */
+    int32_t reserved0;
+    double t_submit, t_admit, t_done;
+    double ms_ingest;     /* generation kernels (gen != 0), HIP events          */
+    sk_solve_info info;
+} sk_result;
+
+typedef struct sk_server_info {
+    int64_t submitted, completed, in_flight, queued;
+    int64_t bytes_in_use, bytes_high_water, budget;
+    int32_t slots, reserved;
+} sk_server_info;
+
+typedef struct sk_server *sk_server_handle;
+
+/*
+ * sk_server_create -- a continuous-batching least-squares server on the
+ * current device.  It allocates one device pool of budget_bytes and
+ * max_slots (1..64) streams, and runs one scheduler thread.  Requests wait
+ * in arrival order; the head is admitted as soon as a slot is free and the
+ * pool has room for its footprint (sk_server_footprint), so requests that
+ * arrive while others run join them on the device; each admitted request
+ * advances on its own stream, interleaved with the others, and releases its
+ * memory when done.  Errors: SK_EINVAL, SK_ENOMEM, SK_EHIP.
+ */
+int sk_server_create(size_t budget_bytes, int32_t max_slots, sk_server_handle *out);
+
+/* sk_server_footprint -- device bytes a request holds while admitted. */
+int sk_server_footprint(const sk_request *req, size_t *bytes);
+
+/*
+ * sk_server_submit -- queue a request (copied); *ticket identifies it.
+ * Errors: SK_EINVAL (validation as in sketch_solve), SK_EADMIT (footprint
+ * larger than the budget: it could never run), SK_EBUSY (shutting down).
+ */
+int sk_server_submit(sk_server_handle srv, const sk_request *req, uint64_t *ticket);
+
+/*
+ * sk_server_poll -- *done = 1 and *out filled once the request finished
+ * (the ticket is then forgotten), else *done = 0.  sk_server_wait blocks
+ * until done.  Errors: SK_EINVAL (unknown ticket).
+ */
+int sk_server_poll(sk_server_handle srv, uint64_t ticket, int32_t *done, sk_result *out);
+int sk_server_wait(sk_server_handle srv, uint64_t ticket, sk_result *out);
+
+/* sk_server_stats -- counters and the pool's high-water mark. */
+int sk_server_stats(sk_server_handle srv, sk_server_info *out);
+
+/* sk_server_clock -- seconds since the server was created. */
+double sk_server_clock(sk_server_handle srv);
+
+/* sk_server_destroy -- finish queued and running requests, then free all. */
+int sk_server_destroy(sk_server_handle srv);
+
+/*
+ * sk_server_simulate -- the server's admission policy on the host only, as a
+ * discrete-event simulation (a testing export; no device is used): request k
+ * arrives at arrive[k] (non-decreasing), holds footprint[k] bytes and runs
+ * for service[k] seconds once admitted; returns admit[k] and done[k].
+ * Errors: SK_EINVAL, SK_EADMIT (a footprint above the budget).
+ */
+int sk_server_simulate(size_t budget_bytes, int32_t max_slots, int32_t count, const double *arrive,
+                       const uint64_t *footprint, const double *service, double *admit, double *done);
 
 /* sketch_last_error -- message of the last failure on this thread ("" if none). */
 const char *sketch_last_error(void);

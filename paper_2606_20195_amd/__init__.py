@@ -13,9 +13,9 @@ from __future__ import annotations
 import ctypes
 
 from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, ENOTCONV, F16, F32,
-                   Problem, Schedule, SketchError, SolveInfo, SolveOpts, check, load)
+                   Problem, Request, Result, Schedule, ServerInfo, SketchError, SolveInfo, SolveOpts, check, load)
 
-__all__ = ["Sketch", "SketchError", "Schedule", "Batch", "tune_batch", "load_tuning", "clear_tuning", "quantize",
+__all__ = ["Sketch", "SketchError", "Schedule", "Batch", "Server", "simulate_admission", "tune_batch", "load_tuning", "clear_tuning", "quantize",
            "qr_f32", "trinv_f32", "version", "ACC_F32",
            "ACC_F16_RN",
            "ACC_F16_SR", "ACC_F16_DITHER", "F32", "F16", "BF16", "ACCUMULATE"]
@@ -232,6 +232,96 @@ def load_tuning(path):
 
 def clear_tuning():
     check(load().sketch_clear_tuning(), "sketch_clear_tuning")
+
+
+class Server:
+    """Continuous-batching least-squares server (sk_server_* in the C ABI)."""
+
+    def __init__(self, budget_bytes, slots=4):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        check(self._lib.sk_server_create(int(budget_bytes), int(slots), ctypes.byref(h)), "sk_server_create")
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def request(m, n, d, s=4, seed=0, rounding=ACC_F16_RN, A=None, b=None, x=None, a_dtype=None, gen=0,
+                gen_seed=0, tol=0.0, inner_tol=0.0, max_refine=0, max_inner=0, epoch=0):
+        """A Request; A/b are device tensors (gen = 0) or None (generated)."""
+        torch = _torch()
+        if a_dtype is None:
+            a_dtype = _dtype_code(A) if A is not None else F16
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+        r = Request(int(m), int(n), int(d), int(s), int(rounding), int(seed) & (2 ** 64 - 1), int(a_dtype),
+                    int(gen), A.data_ptr() if A is not None else None, _matrix(A, "A") if A is not None else 0,
+                    b.data_ptr() if b is not None else None, x.data_ptr(), int(gen_seed) & (2 ** 64 - 1),
+                    SolveOpts(float(tol), float(inner_tol), int(max_refine), int(max_inner),
+                              int(epoch) & 0xFFFFFFFF))
+        return r, (A, b, x)
+
+    def submit(self, req, keep=()):
+        t = ctypes.c_uint64()
+        check(self._lib.sk_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "sk_server_submit")
+        self._keep[t.value] = keep           # tensors stay alive until the result is collected
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        res = Result()
+        check(self._lib.sk_server_poll(self._h, int(ticket), ctypes.byref(done), ctypes.byref(res)),
+              "sk_server_poll")
+        if not done.value:
+            return None
+        self._keep.pop(int(ticket), None)
+        return res.as_dict()
+
+    def wait(self, ticket):
+        res = Result()
+        check(self._lib.sk_server_wait(self._h, int(ticket), ctypes.byref(res)), "sk_server_wait")
+        self._keep.pop(int(ticket), None)
+        return res.as_dict()
+
+    def stats(self):
+        info = ServerInfo()
+        check(self._lib.sk_server_stats(self._h, ctypes.byref(info)), "sk_server_stats")
+        return info.as_dict()
+
+    def clock(self):
+        return self._lib.sk_server_clock(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sk_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint(req):
+    n = ctypes.c_size_t()
+    check(load().sk_server_footprint(ctypes.byref(req), ctypes.byref(n)), "sk_server_footprint")
+    return n.value
+
+
+def simulate_admission(budget, slots, arrive, footprints, service):
+    """Host-only replay of the server's admission policy: (admit, done) times."""
+    import numpy as np
+    k = len(arrive)
+    arrive = np.ascontiguousarray(arrive, dtype=np.float64)
+    fp = np.ascontiguousarray(footprints, dtype=np.uint64)
+    sv = np.ascontiguousarray(service, dtype=np.float64)
+    admit = np.zeros(k)
+    done = np.zeros(k)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # noqa: E731
+    check(load().sk_server_simulate(int(budget), int(slots), k, ptr(arrive), ptr(fp), ptr(sv), ptr(admit),
+                                    ptr(done)), "sk_server_simulate")
+    return admit, done
 
 
 def qr_f32(M, k, stream=None):

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsketch.so")
 
 # return codes (include/sketch.h)
-OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOTCONV = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOTCONV, EADMIT, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F16, BF16 = 0, 1, 2
 ACC_F32, ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER = 0, 1, 2, 3
 ACCUMULATE = 1
@@ -23,7 +23,9 @@ EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedu
            "sketch_hash", "sketch_quantize", "sketch_solve", "sketch_qr_f32", "sketch_trinv_f32",
            "sketch_batch_create", "sketch_batch_apply", "sketch_batch_graph", "sketch_batch_schedule",
            "sketch_batch_destroy", "sketch_apply_batched", "sketch_tune_batch", "sketch_tune_apply",
-           "sketch_load_tuning", "sketch_clear_tuning", "sketch_last_error", "sketch_version")
+           "sketch_load_tuning", "sketch_clear_tuning", "sk_server_create", "sk_server_footprint",
+           "sk_server_submit", "sk_server_poll", "sk_server_wait", "sk_server_stats", "sk_server_clock",
+           "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version")
 
 
 class Schedule(ctypes.Structure):
@@ -57,6 +59,35 @@ class SolveInfo(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("s", ctypes.c_int32),
+                ("rounding", ctypes.c_int32), ("seed", ctypes.c_uint64), ("a_dtype", ctypes.c_int32),
+                ("gen", ctypes.c_int32), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("gen_seed", ctypes.c_uint64), ("opts", SolveOpts),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("ms_ingest", ctypes.c_double),
+                ("info", SolveInfo)]
+
+    def as_dict(self):
+        d = dict(status=self.status, t_submit=self.t_submit, t_admit=self.t_admit, t_done=self.t_done,
+                 ms_ingest=self.ms_ingest)
+        d.update(self.info.as_dict())
+        return d
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("bytes_in_use", ctypes.c_int64), ("bytes_high_water", ctypes.c_int64),
+                ("budget", ctypes.c_int64), ("slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class SketchError(RuntimeError):
@@ -102,6 +133,15 @@ def load():
                               ctypes.c_int),
         "sketch_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
         "sketch_clear_tuning": ([], ctypes.c_int),
+        "sk_server_create": ([ctypes.c_size_t, i32, ctypes.POINTER(P)], ctypes.c_int),
+        "sk_server_footprint": ([ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "sk_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], ctypes.c_int),
+        "sk_server_poll": ([P, u64, ctypes.POINTER(i32), ctypes.POINTER(Result)], ctypes.c_int),
+        "sk_server_wait": ([P, u64, ctypes.POINTER(Result)], ctypes.c_int),
+        "sk_server_stats": ([P, ctypes.POINTER(ServerInfo)], ctypes.c_int),
+        "sk_server_clock": ([P], ctypes.c_double),
+        "sk_server_destroy": ([P], ctypes.c_int),
+        "sk_server_simulate": ([ctypes.c_size_t, i32, i32, P, P, P, P, P], ctypes.c_int),
         "sketch_last_error": ([], ctypes.c_char_p),
         "sketch_version": ([], ctypes.c_int),
     }

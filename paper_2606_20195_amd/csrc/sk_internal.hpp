@@ -88,6 +88,19 @@ hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, i
                        int32_t *buckets, int8_t *signs, hipStream_t st);
 void solve_release(sk_sketch *h);
 
+// A least-squares solve as resumable asynchronous phases (sk_solve.hip).
+struct SolveJob;
+SolveJob *job_new();
+void job_delete(SolveJob *j);
+// Validate and plan; *footprint = device bytes needed at the job's base.
+int job_prepare(SolveJob *j, const sk_sketch &S, const void *A, int32_t a_dtype, int64_t n, int64_t lda,
+                const double *b, double *x, const sk_solve_opts *opts, size_t *footprint);
+// Bind to device memory and a stream; enqueue the first phases.
+int job_start(SolveJob *j, void *device_base, hipStream_t st);
+// 1 while in flight, SK_OK / SK_ENOTCONV when finished, other codes on failure.
+int job_step(SolveJob *j, bool block);
+void job_info(const SolveJob *j, sk_solve_info *info);
+
 // Tuning table (filled by the autotuners, read by the planners).
 std::string apply_key(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n);
 bool tuning_lookup(const std::string &key, sk_schedule *out);

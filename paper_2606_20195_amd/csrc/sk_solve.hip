@@ -990,14 +990,362 @@ hipError_t launch_rows(int a_dtype, bool resid, const Geo& g, const RowArgs& a, 
 
 }  // namespace
 
-// Device workspace of sketch_solve, grown on demand.
+// ------------------------------------------------------------ solve jobs
+
+// One least-squares solve as a resumable sequence of asynchronous phases on
+// one stream.  job_step() never blocks unless asked to: it looks at the event
+// recorded after the last state copy and, once the device is there, reads
+// the state and enqueues the next phase.  sketch_solve drives one job to the
+// end; the request server keeps one job per slot and interleaves them.
+struct SolveJob {
+    // problem
+    sk_sketch S;                 // the S of A (no workspace of its own)
+    sk_sketch Sb;                // the same S in FP32 mode, for b
+    const void* A = nullptr;
+    int32_t a_dtype = 0;
+    int64_t n = 0, lda = 0;
+    const double* b = nullptr;
+    double* x = nullptr;
+    sk_solve_opts o{};
+    // plan
+    bool f16 = false;
+    int64_t ldm = 0, ld16 = 0;
+    int nwg = 0;
+    Geo geo;
+    RowArgs ra{};
+    size_t oM = 0, o16 = 0, ob32 = 0, ou = 0, oP = 0, oPT = 0, otau = 0, ot = 0, ov = 0, ow = 0, oy = 0, opart = 0,
+           ost = 0, otk = 0, total = 0;
+    // device binding
+    hipStream_t st = nullptr;
+    char* base = nullptr;
+    float* Mw = nullptr;
+    uint16_t* SA16 = nullptr;
+    float* b32 = nullptr;
+    float* tau = nullptr;
+    // host resources (kept across reuses)
+    SolveState* host = nullptr;  // pinned
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_state = nullptr;
+    // progress
+    int phase = 0;               // 0 idle, 1 residual in flight, 2 LSQR in flight, 3 finishing, 4 done
+    int k = 0, launched = 0, steps = 0;
+    double rel0 = 0.0;
+    bool converged = false;
+    int rc = SK_OK;
+};
+
+SolveJob* job_new() { return new (std::nothrow) SolveJob; }
+
+void job_delete(SolveJob* j)
+{
+    if (!j) return;
+    if (j->host) (void)hipHostFree(j->host);
+    for (hipEvent_t& e : j->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (j->ev_state) (void)hipEventDestroy(j->ev_state);
+    if (j->Sb.ws) (void)hipFree(j->Sb.ws);
+    delete j;
+}
+
+// Validate and plan; no device memory is touched.  *footprint = device bytes
+// the job needs at its base pointer.
+int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype, int64_t n, int64_t lda,
+                const double* b, double* x, const sk_solve_opts* opts, size_t* footprint)
+{
+    const int esz = a_dtype == SK_F32 ? 4 : (a_dtype == SK_F16 || a_dtype == SK_BF16) ? 2 : 0;
+    if (!esz) return set_error(SK_EINVAL, "unknown element type %d", a_dtype);
+    if (n < 1 || lda < n) return set_error(SK_EINVAL, "bad shape n=%lld lda=%lld", (long long)n, (long long)lda);
+    if (n > S.d) return set_error(SK_EINVAL, "n = %lld exceeds the sketch size d = %lld", (long long)n,
+                                  (long long)S.d);
+    if (n > kMaxN) return set_error(SK_EUNSUPPORTED, "n = %lld > %d", (long long)n, kMaxN);
+    if (S.d > kMaxD) return set_error(SK_EUNSUPPORTED, "d = %lld > %lld", (long long)S.d, (long long)kMaxD);
+    if (!A || !b || !x) return set_error(SK_EINVAL, "NULL array");
+    if ((uintptr_t)A % (uintptr_t)esz) return set_error(SK_EINVAL, "A is not element aligned");
+    if (((uintptr_t)b | (uintptr_t)x) & 7u) return set_error(SK_EINVAL, "b and x must be 8-byte aligned");
+    sk_solve_opts o{};
+    if (opts) {
+        o = *opts;
+        for (int i = 0; i < 3; ++i)
+            if (o.reserved[i]) return set_error(SK_EINVAL, "reserved option fields must be zero");
+        if (o.tol < 0 || o.inner_tol < 0 || o.max_refine < 0 || o.max_inner < 0)
+            return set_error(SK_EINVAL, "negative option");
+    }
+    if (o.tol == 0) o.tol = 1e-10;
+    if (o.inner_tol == 0) o.inner_tol = 1e-6;
+    if (o.max_refine == 0) o.max_refine = 10;
+    if (o.max_inner == 0) o.max_inner = 100;
+
+    DeviceInfo dev;
+    int rc = device_info(&dev);
+    if (rc) return rc;
+    const int64_t m = S.m, d = S.d;
+    const int64_t nwg0 = std::max<int64_t>(1, std::min<int64_t>(dev.cus, (m + 1023) / 1024));
+    const int64_t rpw = (m + nwg0 - 1) / nwg0;
+    if (rpw * lda * esz >= ((int64_t)1 << 31))
+        return set_error(SK_EUNSUPPORTED, "rows per workgroup span more than 2 GiB");
+    j->S = S;
+    j->S.ws = nullptr;
+    j->S.ws_floats = 0;
+    j->S.sw = nullptr;
+    if (j->Sb.ws) (void)hipFree(j->Sb.ws);
+    j->Sb = sk_sketch{};
+    j->Sb.m = S.m;
+    j->Sb.d = S.d;
+    j->Sb.s = S.s;
+    j->Sb.seed = S.seed;
+    j->Sb.rounding = SK_ACC_F32;
+    j->A = A;
+    j->a_dtype = a_dtype;
+    j->n = n;
+    j->lda = lda;
+    j->b = b;
+    j->x = x;
+    j->o = o;
+    j->f16 = S.rounding != SK_ACC_F32;
+    j->ldm = n + 1;
+    j->ld16 = (n + 1) / 2 * 2;
+    j->nwg = (int)((m + rpw - 1) / rpw);          // every workgroup owns at least one row
+    j->geo = row_geometry(esz, n);
+    const int pst = (int)((n + 3 + 3) / 4 * 4);
+
+    size_t off = 0;
+    auto take = [&](size_t b2) { const size_t at = off; off = align_up(off + b2, 256); return at; };
+    j->oM = take((size_t)d * j->ldm * 4);
+    j->o16 = j->f16 ? take((size_t)d * j->ld16 * 2) : 0;
+    j->ob32 = take((size_t)m * 4);
+    j->ou = take((size_t)m * 4);
+    j->oP = take((size_t)n * n * 4);
+    j->oPT = take((size_t)n * n * 4);
+    j->otau = take((size_t)n * 4 + 4);
+    j->ot = take((size_t)n * 4);
+    j->ov = take((size_t)n * 8);
+    j->ow = take((size_t)n * 8);
+    j->oy = take((size_t)n * 8);
+    j->opart = take((size_t)j->nwg * pst * 8);
+    j->ost = take(sizeof(SolveState));
+    j->otk = take(64);
+    j->total = off;
+
+    RowArgs& ra = j->ra;
+    ra = RowArgs{};
+    ra.A = A;
+    ra.lda = lda;
+    ra.m = m;
+    ra.rpw = rpw;
+    ra.n = (int32_t)n;
+    ra.vec = ((lda * esz) % 16 == 0 && (uintptr_t)A % 16 == 0) ? 1 : 0;
+    ra.mask = j->geo.mask;
+    ra.b = b;
+    ra.x = x;
+    ra.ldp = n;
+    ra.pst = pst;
+    j->phase = 0;
+    *footprint = j->total;
+    return SK_OK;
+}
+
+namespace {
+
+int job_fail(SolveJob* j, int rc)
+{
+    j->rc = rc;
+    j->phase = 4;
+    return rc;
+}
+
+// Copy the device state to the pinned slot and mark the point to wait for.
+int job_mark(SolveJob* j)
+{
+    hipError_t e = hipMemcpyAsync(j->host, j->ra.st, sizeof(SolveState), hipMemcpyDeviceToHost, j->st);
+    if (e == hipSuccess) e = hipEventRecord(j->ev_state, j->st);
+    return e == hipSuccess ? SK_OK : hip_err(e, "reading the solver state");
+}
+
+int job_lsqr_batch(SolveJob* j)
+{
+    const int batch = std::min(8, j->o.max_inner - j->launched);
+    for (int i = 0; i < batch; ++i) {
+        hipError_t e = launch_rows(j->a_dtype, false, j->geo, j->ra, j->nwg, j->st);
+        if (e != hipSuccess) return hip_err(e, "LSQR pass");
+    }
+    j->launched += batch;
+    return job_mark(j);
+}
+
+int job_resid(SolveJob* j)
+{
+    j->ra.first = j->k == 0 ? 1 : 0;
+    hipError_t e = launch_rows(j->a_dtype, true, j->geo, j->ra, j->nwg, j->st);
+    if (e != hipSuccess) return hip_err(e, "residual pass");
+    return job_mark(j);
+}
+
+}  // namespace
+
+// Bind the job to device memory (>= its footprint, 256-byte aligned) and a
+// stream, and enqueue sketch, factorisation and the first residual pass.
+int job_start(SolveJob* j, void* device_base, hipStream_t st)
+{
+    hipError_t e;
+    if (!j->host) {
+        if ((e = hipHostMalloc((void**)&j->host, sizeof(SolveState), hipHostMallocDefault)) != hipSuccess) {
+            j->host = nullptr;
+            return set_error(SK_ENOMEM, "pinned status: %s", hipGetErrorString(e));
+        }
+        for (hipEvent_t& ev : j->ev)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_err(e, "hipEventCreate");
+        if ((e = hipEventCreateWithFlags(&j->ev_state, hipEventDisableTiming)) != hipSuccess)
+            return hip_err(e, "hipEventCreate");
+    }
+    j->st = st;
+    j->base = (char*)device_base;
+    char* base = j->base;
+    j->Mw = (float*)(base + j->oM);
+    j->SA16 = (uint16_t*)(base + j->o16);
+    j->b32 = (float*)(base + j->ob32);
+    j->tau = (float*)(base + j->otau);
+    RowArgs& ra = j->ra;
+    ra.u = (float*)(base + j->ou);
+    ra.t = (float*)(base + j->ot);
+    ra.P = (const float*)(base + j->oP);
+    ra.PT = (const float*)(base + j->oPT);
+    ra.v = (double*)(base + j->ov);
+    ra.w = (double*)(base + j->ow);
+    ra.y = (double*)(base + j->oy);
+    ra.part = (double*)(base + j->opart);
+    ra.st = (SolveState*)(base + j->ost);
+    ra.ticket = (uint32_t*)(base + j->otk);
+    j->k = 0;
+    j->launched = 0;
+    j->steps = 0;
+    j->rel0 = 0.0;
+    j->converged = false;
+    j->rc = SK_OK;
+    std::memset(j->host, 0, sizeof(SolveState));
+    const int64_t m = j->S.m, d = j->S.d, n = j->n;
+    int rc;
+
+    // ---- sketch
+    if ((e = hipEventRecord(j->ev[0], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, st, ra.st, j->o.tol, j->o.inner_tol, j->o.max_inner,
+                       ra.ticket);
+    if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "init kernel"));
+    if (j->f16) {
+        rc = sketch_apply(&j->S, j->A, j->a_dtype, m, n, j->lda, 0, j->SA16, j->ld16, 0, j->o.round_epoch, st);
+        if (rc) return job_fail(j, rc);
+        hipLaunchKernelGGL(f16_to_f32_kernel, dim3(256), dim3(256), 0, st, (const uint16_t*)j->SA16, j->ld16, j->Mw,
+                           j->ldm, d, (int32_t)n);
+        if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "convert kernel"));
+    } else {
+        rc = sketch_apply(&j->S, j->A, j->a_dtype, m, n, j->lda, 0, j->Mw, j->ldm, 0, j->o.round_epoch, st);
+        if (rc) return job_fail(j, rc);
+    }
+    hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(1024), dim3(256), 0, st, j->b, j->b32, m);
+    if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "cast kernel"));
+    rc = sketch_apply(&j->Sb, j->b32, SK_F32, m, 1, 1, 0, j->Mw + n, j->ldm, 0, 0, st);
+    if (rc) return job_fail(j, rc);
+    if ((e = hipEventRecord(j->ev[1], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+
+    // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
+    if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
+    if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.P, (float*)ra.PT, n, &ra.st->bad, st)) != hipSuccess)
+        return job_fail(j, hip_err(e, "inverse kernel"));
+    hipLaunchKernelGGL(x0_kernel, dim3(1), dim3(kT), 0, st, ra.PT, (int64_t)n, (int32_t)n, (const float*)j->Mw,
+                       j->ldm, (int32_t)n, j->x);
+    if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "x0 kernel"));
+    if ((e = hipEventRecord(j->ev[2], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+
+    // ---- first residual
+    if ((rc = job_resid(j))) return job_fail(j, rc);
+    j->phase = 1;
+    return SK_OK;
+}
+
+// Advance the job.  Returns 1 while work is in flight, SK_OK when finished
+// successfully (or SK_ENOTCONV), another negative code on failure.
+int job_step(SolveJob* j, bool block)
+{
+    for (;;) {
+        if (j->phase == 4) return j->rc;
+        if (j->phase == 0) return set_error(SK_EINVAL, "solve job not started");
+        hipEvent_t wait = j->phase == 3 ? j->ev[3] : j->ev_state;
+        hipError_t e;
+        if (block) {
+            e = hipEventSynchronize(wait);
+        } else {
+            e = hipEventQuery(wait);
+            if (e == hipErrorNotReady) return 1;
+        }
+        if (e != hipSuccess) return job_fail(j, hip_err(e, "waiting for the solver"));
+        SolveState* h = j->host;
+        int rc;
+        if (j->phase == 3) {
+            j->phase = 4;
+            if (!j->converged)
+                j->rc = set_error(SK_ENOTCONV, "not converged after %d refinement steps: criterion %.3e > %.3e",
+                                  j->steps, h->crit, j->o.tol);
+            return j->rc;
+        }
+        if (h->bad) {
+            return job_fail(j, set_error(SK_EINVAL, j->phase == 1 && j->k == 0
+                                                        ? "SA is numerically rank deficient (zero or non-finite pivot)"
+                                                        : "the solver produced a non-finite value"));
+        }
+        bool finish = false;
+        if (j->phase == 1) {
+            if (j->k == 0) j->rel0 = h->rel;
+            j->steps = j->k;
+            if (h->outer_done) {
+                j->converged = true;
+                finish = true;
+            } else if (j->k == j->o.max_refine) {
+                finish = true;
+            } else {
+                j->launched = 0;
+                if ((rc = job_lsqr_batch(j))) return job_fail(j, rc);
+                j->phase = 2;
+            }
+        } else {   // phase 2: a batch of LSQR iterations
+            if (h->inner_done || j->launched >= j->o.max_inner) {
+                ++j->k;
+                if ((rc = job_resid(j))) return job_fail(j, rc);
+                j->phase = 1;
+            } else if ((rc = job_lsqr_batch(j))) {
+                return job_fail(j, rc);
+            }
+        }
+        if (finish) {
+            if ((e = hipEventRecord(j->ev[3], j->st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+            j->phase = 3;
+        }
+        if (!block) return 1;
+    }
+}
+
+void job_info(const SolveJob* j, sk_solve_info* info)
+{
+    std::memset(info, 0, sizeof(*info));
+    if (j->phase != 4) return;
+    const SolveState* h = j->host;
+    info->converged = j->converged ? 1 : 0;
+    info->refine_steps = j->steps;
+    info->inner_iters = h->total_inner;
+    info->crit = h->crit;
+    info->rel_residual = h->rel;
+    info->rel_residual_x0 = j->rel0;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, j->ev[0], j->ev[1]) == hipSuccess) info->ms_sketch = ms;
+    if (hipEventElapsedTime(&ms, j->ev[1], j->ev[2]) == hipSuccess) info->ms_factor = ms;
+    if (hipEventElapsedTime(&ms, j->ev[2], j->ev[3]) == hipSuccess) info->ms_refine = ms;
+    if (hipEventElapsedTime(&ms, j->ev[0], j->ev[3]) == hipSuccess) info->ms_total = ms;
+}
+
+// Device workspace of sketch_solve, grown on demand, and its job.
 struct SolveWs {
     int device = -1;
     void* base = nullptr;
     size_t bytes = 0;
-    SolveState* host = nullptr;          // pinned copy of the state
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    sk_sketch hb;                        // FP32 sketch of b with the same S
+    SolveJob* job = nullptr;
 };
 
 void solve_release(sk_sketch* h)
@@ -1005,10 +1353,7 @@ void solve_release(sk_sketch* h)
     if (!h || !h->sw) return;
     SolveWs* w = h->sw;
     if (w->base) (void)hipFree(w->base);
-    if (w->host) (void)hipHostFree(w->host);
-    for (hipEvent_t& e : w->ev)
-        if (e) (void)hipEventDestroy(e);
-    if (w->hb.ws) (void)hipFree(w->hb.ws);
+    job_delete(w->job);
     delete w;
     h->sw = nullptr;
 }
@@ -1045,204 +1390,35 @@ int sketch_solve(sk_handle h, const void* A, int32_t a_dtype, int64_t n, int64_t
                  const sk_solve_opts* opts, sk_solve_info* info, void* stream)
 {
     if (!h) return set_error(SK_EINVAL, "handle is NULL");
-    const int esz = a_dtype == SK_F32 ? 4 : (a_dtype == SK_F16 || a_dtype == SK_BF16) ? 2 : 0;
-    if (!esz) return set_error(SK_EINVAL, "unknown element type %d", a_dtype);
-    if (n < 1 || lda < n) return set_error(SK_EINVAL, "bad shape n=%lld lda=%lld", (long long)n, (long long)lda);
-    if (n > h->d) return set_error(SK_EINVAL, "n = %lld exceeds the sketch size d = %lld", (long long)n,
-                                   (long long)h->d);
-    if (n > kMaxN) return set_error(SK_EUNSUPPORTED, "n = %lld > %d", (long long)n, kMaxN);
-    if (h->d > kMaxD) return set_error(SK_EUNSUPPORTED, "d = %lld > %lld", (long long)h->d, (long long)kMaxD);
-    if (!A || !b || !x) return set_error(SK_EINVAL, "NULL array");
-    if ((uintptr_t)A % (uintptr_t)esz) return set_error(SK_EINVAL, "A is not element aligned");
-    if (((uintptr_t)b | (uintptr_t)x) & 7u) return set_error(SK_EINVAL, "b and x must be 8-byte aligned");
-    sk_solve_opts o{};
-    if (opts) {
-        o = *opts;
-        for (int i = 0; i < 3; ++i)
-            if (o.reserved[i]) return set_error(SK_EINVAL, "reserved option fields must be zero");
-        if (o.tol < 0 || o.inner_tol < 0 || o.max_refine < 0 || o.max_inner < 0)
-            return set_error(SK_EINVAL, "negative option");
-    }
-    if (o.tol == 0) o.tol = 1e-10;
-    if (o.inner_tol == 0) o.inner_tol = 1e-6;
-    if (o.max_refine == 0) o.max_refine = 10;
-    if (o.max_inner == 0) o.max_inner = 100;
-
-    DeviceInfo dev;
-    int rc = device_info(&dev);
+    SolveJob probe;
+    size_t need = 0;
+    int rc = job_prepare(&probe, *h, A, a_dtype, n, lda, b, x, opts, &need);
     if (rc) return rc;
-    const int64_t m = h->m, d = h->d;
-    const bool f16 = h->rounding != SK_ACC_F32;
-    const int64_t ldm = n + 1;
-    const int64_t ld16 = (n + 1) / 2 * 2;
-    const int64_t nwg0 = std::max<int64_t>(1, std::min<int64_t>(dev.cus, (m + 1023) / 1024));
-    const int64_t rpw = (m + nwg0 - 1) / nwg0;
-    const int nwg = (int)((m + rpw - 1) / rpw);     // every workgroup owns at least one row
-    if (rpw * lda * esz >= ((int64_t)1 << 31))
-        return set_error(SK_EUNSUPPORTED, "rows per workgroup span more than 2 GiB");
-    const int pst = (int)((n + 3 + 3) / 4 * 4);
-    const Geo geo = row_geometry(esz, n);
-
-    // ---- workspace layout
-    size_t off = 0;
-    auto take = [&](size_t b2) { const size_t at = off; off = align_up(off + b2, 256); return at; };
-    const size_t oM = take((size_t)d * ldm * 4);
-    const size_t o16 = f16 ? take((size_t)d * ld16 * 2) : 0;
-    const size_t ob32 = take((size_t)m * 4);
-    const size_t ou = take((size_t)m * 4);
-    const size_t oP = take((size_t)n * n * 4);
-    const size_t oPT = take((size_t)n * n * 4);
-    const size_t otau = take((size_t)n * 4 + 4);
-    const size_t ot = take((size_t)n * 4);
-    const size_t ov = take((size_t)n * 8);
-    const size_t ow = take((size_t)n * 8);
-    const size_t oy = take((size_t)n * 8);
-    const size_t opart = take((size_t)nwg * pst * 8);
-    const size_t ost = take(sizeof(SolveState));
-    const size_t otk = take(64);
-    const size_t total = off;
-
-    hipError_t e;
     if (!h->sw) {
         h->sw = new (std::nothrow) SolveWs;
         if (!h->sw) return set_error(SK_ENOMEM, "out of host memory");
-        SolveWs* w = h->sw;
-        w->hb.m = h->m;
-        w->hb.d = h->d;
-        w->hb.s = h->s;
-        w->hb.seed = h->seed;
-        w->hb.rounding = SK_ACC_F32;
-        if ((e = hipHostMalloc((void**)&w->host, sizeof(SolveState), hipHostMallocDefault)) != hipSuccess) {
-            w->host = nullptr;
-            return set_error(SK_ENOMEM, "pinned status: %s", hipGetErrorString(e));
-        }
-        for (hipEvent_t& ev : w->ev)
-            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_err(e, "hipEventCreate");
+        h->sw->job = job_new();
+        if (!h->sw->job) return set_error(SK_ENOMEM, "out of host memory");
     }
     SolveWs* w = h->sw;
-    if (w->bytes < total || w->device != dev.device) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+    if (w->bytes < need || w->device != dev) {
         if (w->base) (void)hipFree(w->base);
         w->base = nullptr;
         w->bytes = 0;
-        if ((e = hipMalloc(&w->base, total)) != hipSuccess)
-            return set_error(SK_ENOMEM, "solve workspace of %zu bytes: %s", total, hipGetErrorString(e));
-        w->bytes = total;
-        w->device = dev.device;
+        if ((e = hipMalloc(&w->base, need)) != hipSuccess)
+            return set_error(SK_ENOMEM, "solve workspace of %zu bytes: %s", need, hipGetErrorString(e));
+        w->bytes = need;
+        w->device = dev;
     }
-    char* base = (char*)w->base;
-    float* Mw = (float*)(base + oM);
-    uint16_t* SA16 = (uint16_t*)(base + o16);
-    float* b32 = (float*)(base + ob32);
-    hipStream_t st = (hipStream_t)stream;
-
-    RowArgs ra{};
-    ra.A = A;
-    ra.lda = lda;
-    ra.m = m;
-    ra.rpw = rpw;
-    ra.n = (int32_t)n;
-    ra.vec = ((lda * esz) % 16 == 0 && (uintptr_t)A % 16 == 0) ? 1 : 0;
-    ra.mask = geo.mask;
-    ra.b = b;
-    ra.x = x;
-    ra.u = (float*)(base + ou);
-    ra.t = (float*)(base + ot);
-    ra.P = (const float*)(base + oP);
-    ra.PT = (const float*)(base + oPT);
-    ra.ldp = n;
-    ra.v = (double*)(base + ov);
-    ra.w = (double*)(base + ow);
-    ra.y = (double*)(base + oy);
-    ra.part = (double*)(base + opart);
-    ra.pst = pst;
-    ra.st = (SolveState*)(base + ost);
-    ra.ticket = (uint32_t*)(base + otk);
-    float* tau = (float*)(base + otau);
-    int32_t* bad = &ra.st->bad;
-
-    // ---- sketch
-    if ((e = hipEventRecord(w->ev[0], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, st, ra.st, o.tol, o.inner_tol, o.max_inner,
-                       ra.ticket);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "init kernel");
-    if (f16) {
-        rc = sketch_apply(h, A, a_dtype, m, n, lda, 0, SA16, ld16, 0, o.round_epoch, stream);
-        if (rc) return rc;
-        hipLaunchKernelGGL(f16_to_f32_kernel, dim3(256), dim3(256), 0, st, (const uint16_t*)SA16, ld16, Mw, ldm, d,
-                           (int32_t)n);
-        if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "convert kernel");
-    } else {
-        rc = sketch_apply(h, A, a_dtype, m, n, lda, 0, Mw, ldm, 0, o.round_epoch, stream);
-        if (rc) return rc;
-    }
-    hipLaunchKernelGGL(cast_f64_f32_kernel, dim3(1024), dim3(256), 0, st, b, b32, m);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "cast kernel");
-    rc = sketch_apply(&w->hb, b32, SK_F32, m, 1, 1, 0, Mw + n, ldm, 0, 0, stream);
-    if (rc) return rc;
-    if ((e = hipEventRecord(w->ev[1], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
-
-    // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
-    if ((e = run_qr(Mw, d, n + 1, ldm, n, tau, st)) != hipSuccess) return hip_err(e, "QR kernels");
-    if ((e = run_trinv(Mw, ldm, n, (float*)ra.P, (float*)ra.PT, n, bad, st)) != hipSuccess)
-        return hip_err(e, "inverse kernel");
-    hipLaunchKernelGGL(x0_kernel, dim3(1), dim3(kT), 0, st, ra.PT, (int64_t)n, (int32_t)n, (const float*)Mw, ldm,
-                       (int32_t)n, x);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "x0 kernel");
-    if ((e = hipEventRecord(w->ev[2], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
-
-    // ---- refine
-    auto read_state = [&]() -> int {
-        hipError_t e2 = hipMemcpyAsync(w->host, ra.st, sizeof(SolveState), hipMemcpyDeviceToHost, st);
-        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
-        return e2 == hipSuccess ? SK_OK : hip_err(e2, "reading the solver state");
-    };
-    double rel0 = 0.0;
-    int steps = 0;
-    bool converged = false;
-    for (int k = 0;; ++k) {
-        ra.first = k == 0 ? 1 : 0;
-        if ((e = launch_rows(a_dtype, true, geo, ra, nwg, st)) != hipSuccess) return hip_err(e, "residual pass");
-        if ((rc = read_state())) return rc;
-        if (w->host->bad) return set_error(SK_EINVAL, "SA is numerically rank deficient (zero or non-finite pivot)");
-        if (k == 0) rel0 = w->host->rel;
-        steps = k;
-        if (w->host->outer_done) {
-            converged = true;
-            break;
-        }
-        if (k == o.max_refine) break;
-        ra.first = 0;
-        int launched = 0;
-        while (launched < o.max_inner) {
-            const int batch = std::min(8, o.max_inner - launched);
-            for (int i = 0; i < batch; ++i)
-                if ((e = launch_rows(a_dtype, false, geo, ra, nwg, st)) != hipSuccess) return hip_err(e, "LSQR pass");
-            launched += batch;
-            if ((rc = read_state())) return rc;
-            if (w->host->inner_done) break;
-        }
-        if (w->host->bad) return set_error(SK_EINVAL, "LSQR produced a non-finite value");
-    }
-    if ((e = hipEventRecord(w->ev[3], st)) != hipSuccess) return hip_err(e, "hipEventRecord");
-    if ((e = hipEventSynchronize(w->ev[3])) != hipSuccess) return hip_err(e, "hipEventSynchronize");
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->converged = converged ? 1 : 0;
-        info->refine_steps = steps;
-        info->inner_iters = w->host->total_inner;
-        info->crit = w->host->crit;
-        info->rel_residual = w->host->rel;
-        info->rel_residual_x0 = rel0;
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) info->ms_sketch = ms;
-        if (hipEventElapsedTime(&ms, w->ev[1], w->ev[2]) == hipSuccess) info->ms_factor = ms;
-        if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) info->ms_refine = ms;
-        if (hipEventElapsedTime(&ms, w->ev[0], w->ev[3]) == hipSuccess) info->ms_total = ms;
-    }
-    if (!converged)
-        return set_error(SK_ENOTCONV, "not converged after %d refinement steps: criterion %.3e > %.3e", steps,
-                         w->host->crit, o.tol);
-    return SK_OK;
+    SolveJob* j = w->job;
+    if ((rc = job_prepare(j, *h, A, a_dtype, n, lda, b, x, opts, &need))) return rc;
+    if ((rc = job_start(j, w->base, (hipStream_t)stream))) return rc;
+    rc = job_step(j, true);
+    if (info) job_info(j, info);
+    return rc;
 }
 
 }  // extern "C"
