@@ -50,6 +50,9 @@ def parse():
                         "input with FP32 accumulation; empty = the headline run only")
     p.add_argument("--ls-solves", type=int, default=30, help="timed solves per path in the least-squares leg "
                    "(0 = skip the leg)")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched leg")
+    p.add_argument("--serve", type=int, default=2000, help="measured requests of the serving leg at 200 req/s "
+                   "(after a tenth as many warm-up requests); 0 = skip the leg")
     p.add_argument("--profile-run", action="store_true", help="short fixed sequence for counter passes")
     return p.parse_args()
 
@@ -156,6 +159,128 @@ def ls_leg(nsolves, stream):
     return out
 
 
+def batch_leg(reps=10):
+    """512 independent sketches (m = floor(2^(12 + 8U)), n in {8..128}, d = 4n,
+    s = 4, FP16-RN, A = N(0,1) and every tenth coherent, drawn on the device):
+    one persistent launch, graph replay, and 512 separate sketch_apply calls;
+    the schedule of the persistent launch is autotuned first."""
+    import torch
+    import workloads
+    from paper_2606_20195_amd import ACC_F16_RN, Batch, Sketch, clear_tuning, tune_batch
+    specs_in = workloads.batch_specs()
+    specs, total = [], 0
+    gen = torch.Generator(device="cuda")
+    for sp in specs_in:
+        m, n = sp["m"], sp["n"]
+        # 9.4 GB of inputs: drawn on the device (torch's generator, seed 1000+p) rather than on the host
+        gen.manual_seed(sp["seed"])
+        Ad = torch.randn((m, n), generator=gen, device="cuda", dtype=torch.float32)
+        if sp["kind"] == "coherent":
+            Ad.mul_(1e-3)
+            Ad[:n].zero_()
+            Ad[:n].fill_diagonal_(100.0)
+        Ad = Ad.half()
+        SA = torch.empty((sp["d"], n), dtype=torch.float16, device="cuda")
+        specs.append(dict(A=Ad, SA=SA, d=sp["d"], s=sp["s"], seed=sp["seed"], rounding=ACC_F16_RN))
+        total += m * n * 2 + sp["d"] * n * 2
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    clear_tuning()
+    default_ms = timed(Batch(specs).apply)
+    tuned = tune_batch(specs)
+    b = Batch(specs)
+    ms = timed(b.apply)
+    gms = timed(b.graph)
+    sketches = [Sketch(sp["A"].shape[0], sp["d"], sp["s"], sp["seed"], ACC_F16_RN) for sp in specs]
+
+    def separate():
+        for sk, sp in zip(sketches, specs):
+            sk.apply(sp["A"], SA=sp["SA"])
+    sep_ms = timed(separate)
+    gbs = lambda t: round(total / (t * 1e-3) / 1e9, 1)   # noqa: E731
+    return {"workload": "512 sketches, m = floor(2^(12+8U)), n in {8,16,32,64,128}, d = 4n, s = 4, FP16-RN, "
+                        "10% coherent", "algorithmic_bytes": total,
+            "persistent_ms": round(ms, 4), "persistent_GB/s": gbs(ms),
+            "persistent_pct_of_peak": round(100 * total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1),
+            "graph_ms": round(gms, 4), "graph_GB/s": gbs(gms),
+            "separate_ms": round(sep_ms, 4), "separate_GB/s": gbs(sep_ms),
+            "untuned_persistent_ms": round(default_ms, 4), "tuned_schedule": tuned}
+
+
+def serve_leg(count, warm):
+    """Poisson arrivals of least-squares requests at 200 req/s (m log-uniform
+    in [2^14, 2^22], n in {16, 32, 64, 128, 256}, d = 4n, s = 4, every tenth
+    coherent), generated on the device at admission; FP16 storage with an
+    FP16-RN sketch against the FP32 plain path.  Sojourn = done - arrival,
+    service = done - admission.  Saturation: a backlog of requests submitted
+    at once."""
+    import workloads
+    from paper_2606_20195_amd import ACC_F16_RN, ACC_F32, F16, F32, Server
+    reqs = workloads.arrivals(count + warm)
+    out = {"workload": "Poisson 200 req/s, m log-uniform [2^14, 2^22], n in {16..256}, d = 4n, s = 4, "
+                       "generated on device; stop at ||A^T r||/(||A||_F ||r||) <= 1e-10",
+           "requests": count, "warmup": warm}
+    for name, a_dtype, rounding in (("fp16", F16, ACC_F16_RN), ("fp32_plain", F32, ACC_F32)):
+        srv = Server(24 << 30, slots=4)
+        t_base = srv.clock()
+        tickets = []
+        for k, r in enumerate(reqs):
+            target = t_base + r["t"]
+            while True:
+                now = srv.clock()
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 0.002))
+            req, keep = Server.request(r["m"], r["n"], r["d"], s=r["s"], seed=k, rounding=rounding, a_dtype=a_dtype,
+                                       gen=2 if r["kind"] == "coherent" else 1, gen_seed=r["seed"])
+            tickets.append((srv.submit(req, keep), target))
+        res = [(srv.wait(t), arr) for t, arr in tickets]
+        stats = srv.stats()
+        meas = res[warm:]
+        soj = np.array([r["t_done"] - arr for r, arr in meas]) * 1e3
+        svc = np.array([r["t_done"] - r["t_admit"] for r, _ in meas]) * 1e3
+        span = max(r["t_done"] for r, _ in meas) - min(arr for _, arr in meas)
+        ok = sum(1 for r, _ in meas if r["status"] == 0 and r["converged"] == 1)
+        # saturation: a backlog submitted at once
+        nsat = min(300, len(reqs))
+        t0 = srv.clock()
+        sat = []
+        for k, r in enumerate(reqs[:nsat]):
+            req, keep = Server.request(r["m"], r["n"], r["d"], s=r["s"], seed=k, rounding=rounding, a_dtype=a_dtype,
+                                       gen=2 if r["kind"] == "coherent" else 1, gen_seed=r["seed"])
+            sat.append(srv.submit(req, keep))
+        sres = [srv.wait(t) for t in sat]
+        t1 = max(r["t_done"] for r in sres)
+        srv.close()
+        out[name] = {
+            "solves_per_s_offered": round(len(meas) / span, 2),
+            "sojourn_p50_ms": round(float(np.percentile(soj, 50)), 3),
+            "sojourn_p99_ms": round(float(np.percentile(soj, 99)), 3),
+            "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
+            "service_p99_ms": round(float(np.percentile(svc, 99)), 3),
+            "converged": ok, "measured": len(meas),
+            "ingest_ms_mean": round(float(np.mean([r["ms_ingest"] for r, _ in meas])), 3),
+            "saturation_solves_per_s": round(nsat / (t1 - t0), 2),
+            "hbm_high_water_GiB": round(stats["bytes_high_water"] / 2 ** 30, 3),
+            "budget_GiB": round(stats["budget"] / 2 ** 30, 3),
+        }
+    out["fp16_saturation_speedup"] = round(out["fp16"]["saturation_solves_per_s"]
+                                           / out["fp32_plain"]["saturation_solves_per_s"], 3)
+    return out
+
+
 def profile_run():
     """Fixed short sequence for rocprofv3 counter passes."""
     import torch
@@ -239,7 +364,10 @@ def main():
 
     del A
     torch.cuda.empty_cache()
+    batch = None if args.no_batch else batch_leg()
+    torch.cuda.empty_cache()
     ls = ls_leg(args.ls_solves, stream) if args.ls_solves > 0 else None
+    serve = serve_leg(args.serve, max(1, args.serve // 10)) if args.serve > 0 else None
     traffic = measured_traffic()
     line = {
         "metric": "sketch_apply HBM GB/s (% of peak) + LS solves/s, p50/p99 at 1e-10 residual, FP16 vs FP32",
@@ -265,8 +393,12 @@ def main():
                      "algorithmic_bytes": alg_bytes},
         "modes": modes,
     }
+    if batch is not None:
+        line["batch"] = batch
     if ls is not None:
         line["ls"] = ls
+    if serve is not None:
+        line["serve"] = serve
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -256,6 +256,7 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
+    (void)hipGetLastError();            // launch checks below report this call's errors only
 
     ApplyArgs a{};
     a.A = A;

@@ -422,6 +422,7 @@ void batch_free(sk_batch* b)
 
 hipError_t batch_launch(sk_batch* b, hipStream_t st)
 {
+    (void)hipGetLastError();            // launch checks report this call's errors only
     return launch_batched(b->a_dtype, b->bg, b->vec, b->dual, b->descs, b->count, b->total_items, b->counter,
                           b->grid, b->waves, b->lds_bytes, b->post_scale, b->max_dn, st);
 }

@@ -294,6 +294,7 @@ int start_request(sk_server* srv, Slot& sl, ReqState* q)
     size_t gen_bytes = 0;
     hipError_t e;
     sl.gen_timed = false;
+    (void)hipGetLastError();            // launch checks report this request's errors only
     if (r.gen) {
         const GenLayout g = gen_layout(r);
         gen_bytes = g.bytes;
@@ -343,6 +344,7 @@ void finish_request(sk_server* srv, Slot& sl, int rc)
     if (sl.gen_timed) {
         float ms = 0;
         if (hipEventElapsedTime(&ms, sl.g0, sl.g1) == hipSuccess) q->ms_ingest = ms;
+        (void)hipGetLastError();
     }
     std::lock_guard<std::mutex> lock(srv->mu);
     q->t_done = srv->now();

@@ -56,26 +56,69 @@ struct SolveState {
 
 // ------------------------------------------------------------ reductions
 
+// Sums over aligned groups of W lanes (W a power of two <= 64), every lane of
+// a group receiving the same bits: each step adds a lane's value to its
+// partner's, so both partners add the same two numbers.  Steps within a row
+// of 16 lanes are DPP (quad swaps, half-row and row mirrors), the 16-lane
+// exchange is a ds_swizzle, the 32-lane one v_permlane32_swap.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
 template <int W>
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+    if constexpr (W >= 2) v += __uint_as_float(dpp32<0xB1>(__float_as_uint(v)));    // quad_perm [1,0,3,2]
+    if constexpr (W >= 4) v += __uint_as_float(dpp32<0x4E>(__float_as_uint(v)));    // quad_perm [2,3,0,1]
+    if constexpr (W >= 8) v += __uint_as_float(dpp32<0x141>(__float_as_uint(v)));   // row_half_mirror
+    if constexpr (W >= 16) v += __uint_as_float(dpp32<0x140>(__float_as_uint(v)));  // row_mirror
+    if constexpr (W >= 32) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    if constexpr (W >= 64) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+        v = __int_as_float(r[0]) + __int_as_float(r[1]);
+    }
     return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const uint64_t b = __double_as_longlong(v);
+    const uint64_t lo = dpp32<CTRL>((uint32_t)b), hi = dpp32<CTRL>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
 template <int W>
 __device__ __forceinline__ double group_sum(double v)
 {
-#pragma unroll
-    for (int o = 1; o < W; o <<= 1) v += __shfl_xor(v, o, 64);
+    if constexpr (W >= 2) v += dpp64<0xB1>(v);
+    if constexpr (W >= 4) v += dpp64<0x4E>(v);
+    if constexpr (W >= 8) v += dpp64<0x141>(v);
+    if constexpr (W >= 16) v += dpp64<0x140>(v);
+    if constexpr (W >= 32) {
+        const uint64_t b = __double_as_longlong(v);
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)b, 0x401F);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(b >> 32), 0x401F);
+        v += __longlong_as_double((long long)(lo | (hi << 32)));
+    }
+    if constexpr (W >= 64) {
+        const uint64_t b = __double_as_longlong(v);
+        const auto rl = __builtin_amdgcn_permlane32_swap((int)(uint32_t)b, (int)(uint32_t)b, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap((int)(uint32_t)(b >> 32), (int)(uint32_t)(b >> 32), false,
+                                                         false);
+        const double a0 = __longlong_as_double((long long)((uint64_t)(uint32_t)rl[0] | ((uint64_t)(uint32_t)rh[0] << 32)));
+        const double a1 = __longlong_as_double((long long)((uint64_t)(uint32_t)rl[1] | ((uint64_t)(uint32_t)rh[1] << 32)));
+        v = a0 + a1;
+    }
     return v;
 }
 
+// Sum over groups of 32 or 64 lanes (the QR panel's column groups).
 __device__ __forceinline__ float sum_lanes(float v, int width)
 {
-    for (int o = 1; o < width; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return width == 32 ? group_sum<32>(v) : group_sum<64>(v);
 }
 
 // Sum over all kT threads; every thread receives the total.  `sh` holds kWaves
@@ -158,13 +201,13 @@ struct RowArgs {
     const double* b;
     double* x;                 // FP64 solution (n)
     float* u;                  // m: r in FP32 after a residual pass, then LSQR's unnormalised u
-    float* t;                  // n: P v, the direction of the next LSQR product
-    const float* P;            // n x n, upper triangular
-    const float* PT;           // P^T
+    float* t;                  // n: P v, the direction of the next product by A (FP32 copy of tv)
+    const float* M;            // n x n: P P^T (symmetric, dense)
+    const float* PT;           // P^T (n x n): x0 and nothing per iteration
     int64_t ldp;
-    double* v;                 // LSQR vectors (n each)
-    double* w;
-    double* y;
+    double* tv;                // LSQR in the t = P v form (n each): t, W = P w, Y = P y
+    double* W;
+    double* Y;
     double* part;              // per-workgroup partials, stride pst doubles
     int32_t pst;
     SolveState* st;
@@ -179,76 +222,67 @@ size_t row_lds_bytes(int n, bool fp64)
     return std::max(pass, epi);
 }
 
-// Reduce `nv` values over the workgroup partials into out[0..nv) (LDS).
+// Reduce `nv` values over the workgroup partials into out[0..nv) (LDS).  The
+// loads of one thread are issued eight at a time.
 __device__ void reduce_partials(const double* part, int pst, int nwg, int nv, double* out, double* tmp)
 {
     const int tid = threadIdx.x;
-    if (nv > kT / 2) {
+    const int parts = nv > kT / 2 ? 1 : kT / nv;
+    const int nj = parts == 1 ? (nv + kT - 1) / kT : 1;
+    for (int jj = 0; jj < nj; ++jj) {
+        const int idx = tid + jj * kT;
+        const int j = parts == 1 ? idx : tid % nv;
+        const int q = parts == 1 ? 0 : tid / nv;
+        double acc = 0.0;
+        if (j < nv && q < parts) {
+            double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            int w = q;
+            for (; w + 7 * parts < nwg; w += 8 * parts) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s[e] += part[(int64_t)(w + e * parts) * pst + j];
+            }
+            for (; w < nwg; w += parts) s[0] += part[(int64_t)w * pst + j];
+            acc = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+        }
+        if (parts == 1) {
+            if (j < nv) out[j] = acc;
+        } else if (tid < parts * nv) {
+            tmp[tid] = acc;
+        }
+    }
+    __syncthreads();
+    if (parts > 1) {
         for (int j = tid; j < nv; j += kT) {
-            double s = 0.0;
-            for (int wgi = 0; wgi < nwg; ++wgi) s += part[(int64_t)wgi * pst + j];
-            out[j] = s;
+            double sum = 0.0;
+            for (int q = 0; q < parts; ++q) sum += tmp[q * nv + j];
+            out[j] = sum;
         }
         __syncthreads();
-        return;
     }
-    const int parts = kT / nv;
-    if (tid < parts * nv) {
-        const int j = tid % nv, q = tid / nv;
-        double s0 = 0.0, s1 = 0.0;
-        int wgi = q;
-        for (; wgi + parts < nwg; wgi += 2 * parts) {
-            s0 += part[(int64_t)wgi * pst + j];
-            s1 += part[(int64_t)(wgi + parts) * pst + j];
-        }
-        if (wgi < nwg) s0 += part[(int64_t)wgi * pst + j];
-        tmp[tid] = s0 + s1;
-    }
-    __syncthreads();
-    for (int j = tid; j < nv; j += kT) {
-        double s = 0.0;
-        for (int q = 0; q < parts; ++q) s += tmp[q * nv + j];
-        out[j] = s;
-    }
-    __syncthreads();
 }
 
-// out_j = sum_{k <= j} P[k][j] in_k  (P^T times a vector; in, out in LDS)
-__device__ void mv_PT(const float* P, int64_t ldp, int n, const double* in, double* out, double* tmp)
-{
-    const int tid = threadIdx.x;
-    const int parts = kT / n;
-    if (tid < parts * n) {
-        const int j = tid % n, q = tid / n;
-        double s = 0.0;
-        for (int k = q; k <= j; k += parts) s = fma((double)P[(int64_t)k * ldp + j], in[k], s);
-        tmp[tid] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < n; j += kT) {
-        double s = 0.0;
-        for (int q = 0; q < parts; ++q) s += tmp[q * n + j];
-        out[j] = s;
-    }
-    __syncthreads();
-}
-
-// out_i = sum_{j >= i} P[i][j] in_j  (P times a vector, read through P^T)
-__device__ void mv_P(const float* PT, int64_t ldp, int n, const double* in, double* out, double* tmp)
+// out = S in for an n x n matrix S read through columns (S symmetric, or S
+// given transposed): out_i = sum_j S[j][i] in_j.  Loads issued eight at a time.
+__device__ void matvec_cols(const float* S, int64_t lds_, int n, const double* in, double* out, double* tmp)
 {
     const int tid = threadIdx.x;
     const int parts = kT / n;
     if (tid < parts * n) {
         const int i = tid % n, q = tid / n;
-        double s = 0.0;
-        for (int j = i + q; j < n; j += parts) s = fma((double)PT[(int64_t)j * ldp + i], in[j], s);
-        tmp[tid] = s;
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = q;
+        for (; j + 7 * parts < n; j += 8 * parts) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] = fma((double)S[(int64_t)(j + e * parts) * lds_ + i], in[j + e * parts], s[e]);
+        }
+        for (; j < n; j += parts) s[0] = fma((double)S[(int64_t)j * lds_ + i], in[j], s[0]);
+        tmp[tid] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     }
     __syncthreads();
     for (int i = tid; i < n; i += kT) {
-        double s = 0.0;
-        for (int q = 0; q < parts; ++q) s += tmp[q * n + i];
-        out[i] = s;
+        double sum = 0.0;
+        for (int q = 0; q < parts; ++q) sum += tmp[q * n + i];
+        out[i] = sum;
     }
     __syncthreads();
 }
@@ -268,33 +302,35 @@ __device__ bool last_workgroup(uint32_t* ticket)
     return true;
 }
 
-// LSQR start on min ||A P y - r/||r|| ||, given g = A^T r (LDS, FP64) and
-// ||r|| (Paige-Saunders, Section 4, step 1 with beta_1 u_1 = r/||r||).
-__device__ void lsqr_start(const RowArgs& p, double* g, double rnorm, double* sc)
+// LSQR (Paige and Saunders, Section 4) on A P, kept in the variables
+// t = P v, W = P w, Y = P y so that an iteration needs one product by
+// M = P P^T and no final product: with g = A^T u / beta,
+//   P^T g - beta v = q,  alpha^2 = ||q||^2 = g^T M g - 2 beta t^T g + beta^2,
+//   t' = P q / alpha = (M g - beta t) / alpha,
+// and the solution update is x += ||r|| Y.  Start (step 1 with
+// beta_1 u_1 = r / ||r||): g = A^T r / ||r||, alpha_1 = sqrt(g^T M g),
+// t_1 = M g / alpha_1, W = t_1, Y = 0.
+__device__ void lsqr_start(const RowArgs& p, double* g, double rnorm)
 {
     const int n = p.n, tid = threadIdx.x;
-    double* q = g + (n + 4);
-    double* tv = q + (n + 4);
-    double* tmp = tv + (n + 4);
+    double* mg = g + (n + 4);
+    double* tmp = mg + 2 * (n + 4);
     double* sh = tmp + kT;
     const double ib = rnorm > 0.0 ? 1.0 / rnorm : 0.0;
     for (int j = tid; j < n; j += kT) g[j] *= ib;
     __syncthreads();
-    mv_PT(p.P, p.ldp, n, g, q, tmp);
+    matvec_cols(p.M, p.ldp, n, g, mg, tmp);
     double ss = 0.0;
-    for (int j = tid; j < n; j += kT) ss = fma(q[j], q[j], ss);
-    const double alpha = sqrt(block_sum(ss, sh));
+    for (int j = tid; j < n; j += kT) ss = fma(g[j], mg[j], ss);
+    const double alpha = sqrt(fmax(block_sum(ss, sh), 0.0));
     const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
     for (int j = tid; j < n; j += kT) {
-        const double vj = q[j] * ia;
-        q[j] = vj;
-        p.v[j] = vj;
-        p.w[j] = vj;
-        p.y[j] = 0.0;
+        const double tj = mg[j] * ia;
+        p.tv[j] = tj;
+        p.W[j] = tj;
+        p.Y[j] = 0.0;
+        p.t[j] = (float)tj;
     }
-    __syncthreads();
-    mv_P(p.PT, p.ldp, n, q, tv, tmp);
-    for (int j = tid; j < n; j += kT) p.t[j] = (float)tv[j];
     if (tid == 0) {
         SolveState* st = p.st;
         st->alpha = alpha;
@@ -307,33 +343,39 @@ __device__ void lsqr_start(const RowArgs& p, double* g, double rnorm, double* sc
         st->inner_iter = 0;
         st->inner_done = (alpha == 0.0 || rnorm == 0.0) ? 1 : 0;
     }
-    (void)sc;
 }
 
 // FP64 residual pass: r = b - A x, writes r (FP32) into u and reduces A^T r,
 // ||r||^2 (and on the first pass ||A||_F^2, ||b||^2); the last workgroup
-// evaluates the stopping test and starts LSQR.
+// evaluates the stopping test and starts LSQR.  Loads of the next rows are in
+// flight while the current ones are used.
 template <typename AT, int LR, int CP>
 __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
 {
-    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 4 ? 1 : 2;
+    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = 1;
     extern __shared__ double dsh[];
+    __shared__ double xs[kMaxN + 16];          // x in FP64, zero past n
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rs = lane / LR, cl = lane % LR;
     const int n = p.n;
 
-    double xr[CP][C], g[CP][C];
+    // With two or more chunks per lane the A^T r sums live in LDS (each wave
+    // owns a row of red[], each lane its columns) instead of registers.
+    constexpr bool GL = CP >= 2;
+    double* red = dsh;
+    for (int c = tid; c < kMaxN + 16; c += kT) xs[c] = c < n ? p.x[c] : 0.0;
+    if constexpr (GL)
+        for (int c = tid; c < kWaves * n; c += kT) red[c] = 0.0;
+    double g[GL ? 1 : CP][C];
     int col0[CP];
 #pragma unroll
     for (int pp = 0; pp < CP; ++pp) {
         col0[pp] = C * (cl + LR * pp);
 #pragma unroll
-        for (int e = 0; e < C; ++e) {
-            const int c = col0[pp] + e;
-            xr[pp][e] = c < n ? p.x[c] : 0.0;
-            g[pp][e] = 0.0;
-        }
+        for (int e = 0; e < C; ++e)
+            if constexpr (!GL) g[pp][e] = 0.0;
     }
+    __syncthreads();
     const int64_t row0 = (int64_t)blockIdx.x * p.rpw;
     const int64_t row1 = row0 >= p.m ? row0 : (row0 + p.rpw < p.m ? row0 + p.rpw : p.m);
     const uint32_t rowbytes = (uint32_t)(p.lda * B);
@@ -344,9 +386,9 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
     double rr = 0.0, aa = 0.0, bb = 0.0;
     const int64_t step = (int64_t)kWaves * RW;
 
-    for (int64_t rb = row0 + (int64_t)wave * RW; rb < row1; rb += U * step) {
-        float a[U][CP][C];
-        double bv[U];
+    float aA[U][CP][C], aB[U][CP][C];
+    double bA[U], bB[U];
+    auto load = [&](float (&a)[U][CP][C], double (&bv)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
@@ -356,6 +398,8 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
             for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
             bv[uu] = valid ? p.b[row] : 0.0;
         }
+    };
+    auto use = [&](float (&a)[U][CP][C], const double (&bv)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
@@ -366,7 +410,8 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
 #pragma unroll
                 for (int e = 0; e < C; ++e) {
                     if (mask && col0[pp] + e >= n) a[uu][pp][e] = 0.0f;
-                    dot = fma((double)a[uu][pp][e], xr[pp][e], dot);
+                    const int c = min(col0[pp] + e, kMaxN + 15);
+                    dot = fma((double)a[uu][pp][e], xs[c], dot);
                 }
             dot = group_sum<LR>(dot);
             const double r = valid ? bv[uu] - dot : 0.0;
@@ -375,7 +420,14 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
 #pragma unroll
             for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
-                for (int e = 0; e < C; ++e) g[pp][e] = fma(r, (double)a[uu][pp][e], g[pp][e]);
+                for (int e = 0; e < C; ++e) {
+                    if constexpr (GL) {
+                        const int c = col0[pp] + e;
+                        if (c < n) red[wave * n + c] = fma(r, (double)a[uu][pp][e], red[wave * n + c]);
+                    } else {
+                        g[pp][e] = fma(r, (double)a[uu][pp][e], g[pp][e]);
+                    }
+                }
             if (first) {
                 if (cl == 0) bb = fma(bv[uu], bv[uu], bb);
 #pragma unroll
@@ -384,25 +436,42 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
                     for (int e = 0; e < C; ++e) aa = fma((double)a[uu][pp][e], (double)a[uu][pp][e], aa);
             }
         }
+    };
+    int64_t rb = row0 + (int64_t)wave * RW;
+    if (rb < row1) load(aA, bA, rb);
+    while (rb < row1) {
+        int64_t nx = rb + U * step;
+        if (nx < row1) load(aB, bB, nx);
+        use(aA, bA, rb);
+        if (nx >= row1) break;
+        rb = nx;
+        nx = rb + U * step;
+        if (nx < row1) load(aA, bA, nx);
+        use(aB, bB, rb);
+        if (nx >= row1) break;
+        rb = nx;
     }
     // column sums: over the RW row slots of the wave, then over the waves
+    if constexpr (!GL) {
 #pragma unroll
-    for (int o = LR; o < 64; o <<= 1)
+        for (int o = LR; o < 64; o <<= 1)
 #pragma unroll
-        for (int pp = 0; pp < CP; ++pp)
+            for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
-            for (int e = 0; e < C; ++e) g[pp][e] += __shfl_xor(g[pp][e], o, 64);
+                for (int e = 0; e < C; ++e) g[pp][e] += __shfl_xor(g[pp][e], o, 64);
+    }
     rr = group_sum<64>(rr);
     aa = group_sum<64>(aa);
     bb = group_sum<64>(bb);
-    double* red = dsh;
     __shared__ double wsum[kWaves][3];
-    if (rs == 0) {
+    if constexpr (!GL) {
+        if (rs == 0) {
 #pragma unroll
-        for (int pp = 0; pp < CP; ++pp)
+            for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
-            for (int e = 0; e < C; ++e)
-                if (col0[pp] + e < n) red[wave * n + col0[pp] + e] = g[pp][e];
+                for (int e = 0; e < C; ++e)
+                    if (col0[pp] + e < n) red[wave * n + col0[pp] + e] = g[pp][e];
+        }
     }
     if (lane == 0) {
         wsum[wave][0] = rr;
@@ -453,17 +522,17 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
         if (!(crit == crit) || !(rnorm == rnorm)) st->bad = 2;
     }
     if (done) return;
-    lsqr_start(p, g64, rnorm, sh);
+    lsqr_start(p, g64, rnorm);
 }
 
 // One LSQR iteration (Paige-Saunders, Section 4, steps 3-6) on the operator
-// A P: u' = A t - coef u (t = P v, u = beta u' from the previous iteration),
-// A^T u' and ||u'||^2 in the same pass; the last workgroup finishes the
-// iteration and, at termination, adds ||r|| P y to x in FP64.
+// A P: u' = A t - coef u (u = beta u' from the previous iteration), A^T u' and
+// ||u'||^2 in the same pass; the last workgroup finishes the iteration in the
+// t-form of lsqr_start and, at termination, adds ||r|| Y to x in FP64.
 template <typename AT, int LR, int CP>
 __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
 {
-    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 4 ? 1 : (CP == 2 ? 2 : 4);
+    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 2 ? 1 : 4;
     extern __shared__ double dsh[];
     SolveState* st = p.st;
     if (st->inner_done != 0 || st->outer_done != 0) return;
@@ -494,9 +563,9 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
     float ss = 0.0f;
     const int64_t step = (int64_t)kWaves * RW;
 
-    for (int64_t rb = row0 + (int64_t)wave * RW; rb < row1; rb += U * step) {
-        float a[U][CP][C];
-        float uo[U];
+    float aA[U][CP][C], aB[U][CP][C];
+    float uA[U], uB[U];
+    auto load = [&](float (&a)[U][CP][C], float (&uo)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
@@ -506,6 +575,8 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
             for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
             uo[uu] = valid ? p.u[row] : 0.0f;
         }
+    };
+    auto use = [&](float (&a)[U][CP][C], const float (&uo)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
@@ -527,6 +598,20 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
 #pragma unroll
                 for (int e = 0; e < C; ++e) g[pp][e] = __builtin_fmaf(un, a[uu][pp][e], g[pp][e]);
         }
+    };
+    int64_t rb = row0 + (int64_t)wave * RW;
+    if (rb < row1) load(aA, uA, rb);
+    while (rb < row1) {
+        int64_t nx = rb + U * step;
+        if (nx < row1) load(aB, uB, nx);
+        use(aA, uA, rb);
+        if (nx >= row1) break;
+        rb = nx;
+        nx = rb + U * step;
+        if (nx < row1) load(aA, uA, nx);
+        use(aB, uB, rb);
+        if (nx >= row1) break;
+        rb = nx;
     }
 #pragma unroll
     for (int o = LR; o < 64; o <<= 1)
@@ -563,9 +648,8 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
 
     // ---- epilogue (one workgroup)
     double* g64 = dsh;                       // A^T u' (n), ||u'||^2
-    double* q = g64 + (n + 4);
-    double* tv = q + (n + 4);
-    double* tmp = tv + (n + 4);
+    double* mg = g64 + (n + 4);
+    double* tmp = mg + 2 * (n + 4);
     double* sh = tmp + kT;
     reduce_partials(p.part, p.pst, gridDim.x, n + 1, g64, tmp);
     const double beta = sqrt(g64[n]);
@@ -574,14 +658,15 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
     const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
     for (int j = tid; j < n; j += kT) g64[j] *= ib;
     __syncthreads();
-    mv_PT(p.P, p.ldp, n, g64, q, tmp);
-    double qs = 0.0;
+    matvec_cols(p.M, p.ldp, n, g64, mg, tmp);
+    double s_gmg = 0.0, s_tg = 0.0;
     for (int j = tid; j < n; j += kT) {
-        const double qj = q[j] - beta * p.v[j];
-        q[j] = qj;
-        qs = fma(qj, qj, qs);
+        s_gmg = fma(g64[j], mg[j], s_gmg);
+        s_tg = fma(p.tv[j], g64[j], s_tg);
     }
-    const double alpha = sqrt(block_sum(qs, sh));
+    const double gmg = block_sum(s_gmg, sh);
+    const double tg = block_sum(s_tg, sh);
+    const double alpha = sqrt(fmax(gmg - 2.0 * beta * tg + beta * beta, 0.0));
     const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
     // plane rotation (no damping)
     const double rhobar0 = st->rhobar, phibar0 = st->phibar;
@@ -594,14 +679,6 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
     const double phibar = sn * phibar0;
     const double t1 = rho > 0.0 ? phi / rho : 0.0;
     const double t2 = rho > 0.0 ? -theta / rho : 0.0;
-    for (int j = tid; j < n; j += kT) {
-        const double vj = q[j] * ia;
-        const double wj = p.w[j];
-        p.y[j] = fma(t1, wj, p.y[j]);
-        p.w[j] = fma(t2, wj, vj);
-        p.v[j] = vj;
-        q[j] = vj;
-    }
     const int iter = st->inner_iter + 1;
     const double itol = st->inner_tol;
     // Stopping: the correction problem's normal-equations residual
@@ -612,19 +689,17 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
     // almost orthogonal to the range of A, and a test relative to ||r^|| would
     // stop after one iteration.
     const double test2 = st->alpha1 > 0.0 ? phibar * alpha * fabs(c) / st->alpha1 : 0.0;
-    const double test1 = phibar;
-    const bool done = beta == 0.0 || alpha == 0.0 || test2 <= itol || test1 <= itol || iter >= st->max_inner;
-    __syncthreads();
-    if (!done) {
-        mv_P(p.PT, p.ldp, n, q, tv, tmp);
-        for (int j = tid; j < n; j += kT) p.t[j] = (float)tv[j];
-    } else {
-        // x += ||r|| P y in FP64
-        for (int j = tid; j < n; j += kT) q[j] = p.y[j];
-        __syncthreads();
-        mv_P(p.PT, p.ldp, n, q, tv, tmp);
-        const double scale = st->beta1;
-        for (int j = tid; j < n; j += kT) p.x[j] = fma(scale, tv[j], p.x[j]);
+    const bool done = beta == 0.0 || alpha == 0.0 || test2 <= itol || phibar <= itol || iter >= st->max_inner;
+    const double scale = st->beta1;
+    for (int j = tid; j < n; j += kT) {
+        const double tn = (mg[j] - beta * p.tv[j]) * ia;      // P v_{k+1}
+        const double wj = p.W[j];
+        const double yj = fma(t1, wj, p.Y[j]);
+        p.W[j] = fma(t2, wj, tn);
+        p.tv[j] = tn;
+        p.t[j] = (float)tn;
+        if (done) p.x[j] = fma(scale, yj, p.x[j]);
+        else p.Y[j] = yj;
     }
     if (tid == 0) {
         st->alpha = alpha;
@@ -637,6 +712,18 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
         st->inner_done = done ? 1 : 0;
         if (!(alpha == alpha) || !(beta == beta)) st->bad = 2;
     }
+}
+
+// M = P P^T from P^T (n x n): M[i][j] = sum_k PT[k][i] PT[k][j], k >= max(i, j),
+// accumulated in FP64 and stored in FP32.
+__global__ void gram_kernel(const float* PT, int64_t ldp, int32_t n, float* M)
+{
+    const int i = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (i >= n || j >= n) return;
+    double s = 0.0;
+    for (int k = max(i, j); k < n; ++k) s = fma((double)PT[(int64_t)k * ldp + i], (double)PT[(int64_t)k * ldp + j], s);
+    M[(int64_t)i * ldp + j] = (float)s;
 }
 
 // ------------------------------------------------------------ QR (FP32)
@@ -661,8 +748,14 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
     for (int j = 0; j < nb; ++j) {
         if (grp == j) {
             float* x = pan + j * ldl;
-            float sig = 0.0f;
-            for (int r = j + 1 + gl; r < rows; r += G) sig = __builtin_fmaf(x[r], x[r], sig);
+            float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int r = j + 1 + gl;
+            for (; r + 3 * G < rows; r += 4 * G) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s4[e] = __builtin_fmaf(x[r + e * G], x[r + e * G], s4[e]);
+            }
+            for (; r < rows; r += G) s4[0] = __builtin_fmaf(x[r], x[r], s4[0]);
+            float sig = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             sig = sum_lanes(sig, G);
             const float x0 = x[j];
             float t = 0.0f, beta = x0;
@@ -683,8 +776,14 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
             if (t != 0.0f) {
                 const float* v = pan + j * ldl;
                 float* yc = pan + grp * ldl;
-                float w = gl == 0 ? yc[j] : 0.0f;
-                for (int r = j + 1 + gl; r < rows; r += G) w = __builtin_fmaf(v[r], yc[r], w);
+                float w4[4] = {gl == 0 ? yc[j] : 0.0f, 0.0f, 0.0f, 0.0f};
+                int r = j + 1 + gl;
+                for (; r + 3 * G < rows; r += 4 * G) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w4[e] = __builtin_fmaf(v[r + e * G], yc[r + e * G], w4[e]);
+                }
+                for (; r < rows; r += G) w4[0] = __builtin_fmaf(v[r], yc[r], w4[0]);
+                float w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
                 w = sum_lanes(w, G) * t;
                 if (gl == 0) yc[j] -= w;
                 for (int r = j + 1 + gl; r < rows; r += G) yc[r] = __builtin_fmaf(-w, v[r], yc[r]);
@@ -700,34 +799,49 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
 }
 
 // Apply the panel's reflectors H_{k0} .. H_{k0+nb-1} to columns
-// [c0, c0 + ncols) of M; each workgroup owns cb columns held in LDS.
+// [c0, c0 + ncols) of M; each workgroup owns cb columns held in LDS, and (vlds)
+// the panel's reflectors are staged in LDS once, column-major, with the
+// implicit unit diagonal and zeros above it written out.
 __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
                                                          int32_t nb, int32_t c0, int32_t ncols, int32_t cb,
-                                                         const float* tau)
+                                                         const float* tau, int32_t vlds)
 {
-    extern __shared__ float blk[];       // [rows][cb]
+    extern __shared__ float sm[];
     __shared__ float red[2][kUT / 64][kCB];
     const int rows = rows_total - k0;
+    const int ldb = cb + 1;              // odd row stride: lanes of consecutive rows hit distinct banks
+    float* blk = sm;                     // [rows][ldb]
+    float* V = sm + (size_t)rows * ldb;  // [nb][rows]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cbase = c0 + blockIdx.x * cb;
     const int nc = min(cb, c0 + ncols - cbase);
     for (int idx = tid; idx < rows * cb; idx += kUT) {
         const int r = idx / cb, c = idx - r * cb;
-        blk[idx] = c < nc ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
+        blk[r * ldb + c] = c < nc ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
+    }
+    if (vlds) {
+        for (int idx = tid; idx < rows * nb; idx += kUT) {
+            const int r = idx / nb, j = idx - r * nb;
+            V[(size_t)j * rows + r] = r < j ? 0.0f : (r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j]);
+        }
     }
     __syncthreads();
+    auto vval = [&](int j, int r) -> float {
+        if (vlds) return V[(size_t)j * rows + r];
+        return r < j ? 0.0f : (r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j]);
+    };
     for (int j = 0; j < nb; ++j) {
         const float t = tau[k0 + j];
         if (t == 0.0f) continue;
         float acc[kCB];
 #pragma unroll
         for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
-        for (int r = tid; r < rows; r += kUT) {
+        for (int r = j + tid - (j % kUT); r < rows; r += kUT) {
             if (r < j) continue;
-            const float v = r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j];
+            const float v = vval(j, r);
 #pragma unroll
             for (int c = 0; c < kCB; ++c)
-                if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * cb + c], acc[c]);
+                if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * ldb + c], acc[c]);
         }
 #pragma unroll
         for (int c = 0; c < kCB; ++c) {
@@ -738,23 +852,23 @@ __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, i
         float w[kCB];
 #pragma unroll
         for (int c = 0; c < kCB; ++c) {
-            float s = 0.0f;
+            float sum = 0.0f;
 #pragma unroll
-            for (int q = 0; q < kUT / 64; ++q) s += red[j & 1][q][c];
-            w[c] = s * t;
+            for (int q = 0; q < kUT / 64; ++q) sum += red[j & 1][q][c];
+            w[c] = sum * t;
         }
-        for (int r = tid; r < rows; r += kUT) {
+        for (int r = j + tid - (j % kUT); r < rows; r += kUT) {
             if (r < j) continue;
-            const float v = r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j];
+            const float v = vval(j, r);
 #pragma unroll
             for (int c = 0; c < kCB; ++c)
-                if (c < cb) blk[r * cb + c] = __builtin_fmaf(-w[c], v, blk[r * cb + c]);
+                if (c < cb) blk[r * ldb + c] = __builtin_fmaf(-w[c], v, blk[r * ldb + c]);
         }
     }
     __syncthreads();
     for (int idx = tid; idx < rows * cb; idx += kUT) {
         const int r = idx / cb, c = idx - r * cb;
-        if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[idx];
+        if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[r * ldb + c];
     }
 }
 
@@ -822,7 +936,7 @@ __global__ __launch_bounds__(kT) void x0_kernel(const float* PT, int64_t ldp, in
     __shared__ double tmp[kT];
     for (int j = threadIdx.x; j < n; j += kT) z[j] = (double)M[(int64_t)j * ldm + zc];
     __syncthreads();
-    mv_P(PT, ldp, n, z, out, tmp);
+    matvec_cols(PT, ldp, n, z, out, tmp);       // out_i = sum_j P[i][j] z_j
     for (int j = threadIdx.x; j < n; j += kT) x[j] = out[j];
 }
 
@@ -876,7 +990,7 @@ int panel_width(int64_t rows)
 int update_cols(int64_t rows)
 {
     for (int cb : {kCB, 4, 2, 1})
-        if (rows * cb * 4 <= 128 * 1024) return cb;
+        if (rows * (cb + 1) * 4 <= 150 * 1024) return cb;
     return 0;
 }
 
@@ -890,7 +1004,6 @@ hipError_t set_lds(const void* fn, size_t bytes)
 hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float* tau, hipStream_t st)
 {
     hipError_t e;
-    const int cb = update_cols(rows);
     for (int64_t k0 = 0; k0 < k; ) {
         const int64_t prow = rows - k0;
         const int nb = (int)std::min<int64_t>(panel_width(prow), k - k0);
@@ -901,11 +1014,21 @@ hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int64_t c0 = k0 + nb, ncols = cols - c0;
         if (ncols > 0) {
-            const size_t ulds = (size_t)prow * cb * 4;
+            // reflectors in LDS when they fit beside at least 4 columns, else read from L2
+            int cb = 0, vlds = 0;
+            for (int c : {kCB, 4}) {
+                if ((size_t)prow * (c + 1 + nb) * 4 <= 150 * 1024) {
+                    cb = c;
+                    vlds = 1;
+                    break;
+                }
+            }
+            if (!cb) cb = update_cols(prow);
+            const size_t ulds = (size_t)prow * (cb + 1 + (vlds ? nb : 0)) * 4;
             if ((e = set_lds((const void*)qr_update_kernel, ulds)) != hipSuccess) return e;
             hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((ncols + cb - 1) / cb)), dim3(kUT), ulds, st, M,
                                ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0, (int32_t)ncols,
-                               (int32_t)cb, (const float*)tau);
+                               (int32_t)cb, (const float*)tau, (int32_t)vlds);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         k0 += nb;
@@ -1026,6 +1149,7 @@ struct SolveJob {
     SolveState* host = nullptr;  // pinned
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_state = nullptr;
+    uint32_t recorded = 0;       // bit i: ev[i] recorded in this run
     // progress
     int phase = 0;               // 0 idle, 1 residual in flight, 2 LSQR in flight, 3 finishing, 4 done
     int k = 0, launched = 0, steps = 0;
@@ -1146,6 +1270,13 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
 
 namespace {
 
+hipError_t job_record(SolveJob* j, int i)
+{
+    const hipError_t e = hipEventRecord(j->ev[i], j->st);
+    if (e == hipSuccess) j->recorded |= 1u << i;
+    return e;
+}
+
 int job_fail(SolveJob* j, int rc)
 {
     j->rc = rc;
@@ -1207,11 +1338,11 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     RowArgs& ra = j->ra;
     ra.u = (float*)(base + j->ou);
     ra.t = (float*)(base + j->ot);
-    ra.P = (const float*)(base + j->oP);
+    ra.M = (const float*)(base + j->oP);        // P, then M = P P^T in the same place
     ra.PT = (const float*)(base + j->oPT);
-    ra.v = (double*)(base + j->ov);
-    ra.w = (double*)(base + j->ow);
-    ra.y = (double*)(base + j->oy);
+    ra.tv = (double*)(base + j->ov);
+    ra.W = (double*)(base + j->ow);
+    ra.Y = (double*)(base + j->oy);
     ra.part = (double*)(base + j->opart);
     ra.st = (SolveState*)(base + j->ost);
     ra.ticket = (uint32_t*)(base + j->otk);
@@ -1221,12 +1352,14 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     j->rel0 = 0.0;
     j->converged = false;
     j->rc = SK_OK;
+    j->recorded = 0;
+    (void)hipGetLastError();                    // errors reported below are this job's own
     std::memset(j->host, 0, sizeof(SolveState));
     const int64_t m = j->S.m, d = j->S.d, n = j->n;
     int rc;
 
     // ---- sketch
-    if ((e = hipEventRecord(j->ev[0], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+    if ((e = job_record(j, 0)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
     hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, st, ra.st, j->o.tol, j->o.inner_tol, j->o.max_inner,
                        ra.ticket);
     if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "init kernel"));
@@ -1244,16 +1377,19 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "cast kernel"));
     rc = sketch_apply(&j->Sb, j->b32, SK_F32, m, 1, 1, 0, j->Mw + n, j->ldm, 0, 0, st);
     if (rc) return job_fail(j, rc);
-    if ((e = hipEventRecord(j->ev[1], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+    if ((e = job_record(j, 1)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
 
     // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
     if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
-    if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.P, (float*)ra.PT, n, &ra.st->bad, st)) != hipSuccess)
+    if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.M, (float*)ra.PT, n, &ra.st->bad, st)) != hipSuccess)
         return job_fail(j, hip_err(e, "inverse kernel"));
+    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st,
+                       ra.PT, (int64_t)n, (int32_t)n, (float*)ra.M);
+    if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "Gram kernel"));
     hipLaunchKernelGGL(x0_kernel, dim3(1), dim3(kT), 0, st, ra.PT, (int64_t)n, (int32_t)n, (const float*)j->Mw,
                        j->ldm, (int32_t)n, j->x);
     if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "x0 kernel"));
-    if ((e = hipEventRecord(j->ev[2], st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+    if ((e = job_record(j, 2)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
 
     // ---- first residual
     if ((rc = job_resid(j))) return job_fail(j, rc);
@@ -1274,7 +1410,10 @@ int job_step(SolveJob* j, bool block)
             e = hipEventSynchronize(wait);
         } else {
             e = hipEventQuery(wait);
-            if (e == hipErrorNotReady) return 1;
+            if (e == hipErrorNotReady) {
+                (void)hipGetLastError();            // not an error: leave no trace for later launch checks
+                return 1;
+            }
         }
         if (e != hipSuccess) return job_fail(j, hip_err(e, "waiting for the solver"));
         SolveState* h = j->host;
@@ -1315,7 +1454,7 @@ int job_step(SolveJob* j, bool block)
             }
         }
         if (finish) {
-            if ((e = hipEventRecord(j->ev[3], j->st)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
+            if ((e = job_record(j, 3)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
             j->phase = 3;
         }
         if (!block) return 1;
@@ -1333,11 +1472,16 @@ void job_info(const SolveJob* j, sk_solve_info* info)
     info->crit = h->crit;
     info->rel_residual = h->rel;
     info->rel_residual_x0 = j->rel0;
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, j->ev[0], j->ev[1]) == hipSuccess) info->ms_sketch = ms;
-    if (hipEventElapsedTime(&ms, j->ev[1], j->ev[2]) == hipSuccess) info->ms_factor = ms;
-    if (hipEventElapsedTime(&ms, j->ev[2], j->ev[3]) == hipSuccess) info->ms_refine = ms;
-    if (hipEventElapsedTime(&ms, j->ev[0], j->ev[3]) == hipSuccess) info->ms_total = ms;
+    auto span = [&](int a, int b, double* out) {
+        const uint32_t need = (1u << a) | (1u << b);
+        float ms = 0;
+        if ((j->recorded & need) == need && hipEventElapsedTime(&ms, j->ev[a], j->ev[b]) == hipSuccess) *out = ms;
+    };
+    span(0, 1, &info->ms_sketch);
+    span(1, 2, &info->ms_factor);
+    span(2, 3, &info->ms_refine);
+    span(0, 3, &info->ms_total);
+    (void)hipGetLastError();
 }
 
 // Device workspace of sketch_solve, grown on demand, and its job.
