@@ -434,10 +434,14 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         }
         // Software pipeline: the next tile's loads are in flight while the
         // current tile is scattered; unrolled twice to ping-pong the buffers.
-        // Rows past the unit's end load as zero and add nothing.
+        // Rows past the unit's end load as zero and add nothing.  The next
+        // tile is loaded unconditionally (past the last tile every row is out
+        // of the buffer's range and reads zero without touching memory): a
+        // load behind a branch would make the compiler wait for it before
+        // the current tile's values could be used.
         while (tile < ntiles) {
             int64_t nxt = tile + nwaves;
-            if (nxt < ntiles) load_tile(bufB, nxt);
+            load_tile(bufB, min(nxt, ntiles));     // tile ntiles lies wholly past the unit
             if (acc == 2) {
                 if constexpr (ACC == 2) {
                     mag = tile_mag(bufA, mag);
@@ -455,7 +459,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             hash_tile(offB, sgnB, nxt, fixed, fp.xneg);
             tile = nxt;
             nxt = tile + nwaves;
-            if (nxt < ntiles) load_tile(bufA, nxt);
+            load_tile(bufA, min(nxt, ntiles));
             if (acc == 2) {
                 if constexpr (ACC == 2) {
                     mag = tile_mag(bufB, mag);

@@ -738,9 +738,21 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
     const int rows = rows_total - k0;
     const int ldl = rows | 1;            // odd column stride: the transposing stores hit distinct banks
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < rows * nb; idx += kT) {
-        const int r = idx / nb, c = idx - r * nb;
-        pan[c * ldl + r] = M[(int64_t)(k0 + r) * ldm + k0 + c];
+    // staged eight loads at a time per thread
+    for (int base = 0; base < rows * nb; base += 8 * kT) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = base + e * kT + tid;
+            const int r = idx / nb, c = idx - r * nb;
+            v[e] = idx < rows * nb ? M[(int64_t)(k0 + r) * ldm + k0 + c] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = base + e * kT + tid;
+            const int r = idx / nb, c = idx - r * nb;
+            if (idx < rows * nb) pan[c * ldl + r] = v[e];
+        }
     }
     __syncthreads();
     const int G = nb > 16 ? 32 : 64;     // lanes per column group: kT / G >= nb groups
@@ -815,14 +827,37 @@ __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, i
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cbase = c0 + blockIdx.x * cb;
     const int nc = min(cb, c0 + ncols - cbase);
-    for (int idx = tid; idx < rows * cb; idx += kUT) {
-        const int r = idx / cb, c = idx - r * cb;
-        blk[r * ldb + c] = c < nc ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
+    // staged eight loads at a time per thread
+    for (int base = 0; base < rows * cb; base += 8 * kUT) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = base + e * kUT + tid;
+            const int r = idx / cb, c = idx - r * cb;
+            v[e] = (idx < rows * cb && c < nc) ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = base + e * kUT + tid;
+            const int r = idx / cb, c = idx - r * cb;
+            if (idx < rows * cb) blk[r * ldb + c] = v[e];
+        }
     }
     if (vlds) {
-        for (int idx = tid; idx < rows * nb; idx += kUT) {
-            const int r = idx / nb, j = idx - r * nb;
-            V[(size_t)j * rows + r] = r < j ? 0.0f : (r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j]);
+        for (int base = 0; base < rows * nb; base += 8 * kUT) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int idx = base + e * kUT + tid;
+                const int r = idx / nb, j = idx - r * nb;
+                v[e] = (idx < rows * nb && r > j) ? M[(int64_t)(k0 + r) * ldm + k0 + j] : (r == j ? 1.0f : 0.0f);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int idx = base + e * kUT + tid;
+                const int r = idx / nb, j = idx - r * nb;
+                if (idx < rows * nb) V[(size_t)j * rows + r] = v[e];
+            }
         }
     }
     __syncthreads();
@@ -888,10 +923,21 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
     for (int hi = J - 1; hi >= 0; hi -= 16) {
         const int lo = max(0, hi - 15);
         __syncthreads();
-        for (int idx = tid; idx < (hi - lo + 1) * J; idx += kT) {
-            const int rr = idx / J, k = idx - rr * J;
-            const int i = lo + rr;
-            rp[idx] = k >= i ? R[(int64_t)i * ldr + k] : 0.0f;
+        const int cnt = (hi - lo + 1) * J;
+        for (int base = 0; base < cnt; base += 8 * kT) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int idx = base + e * kT + tid;
+                const int rr = idx / J, k = idx - rr * J;
+                const int i = lo + rr;
+                v[e] = (idx < cnt && k >= i) ? R[(int64_t)i * ldr + k] : 0.0f;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int idx = base + e * kT + tid;
+                if (idx < cnt) rp[idx] = v[e];
+            }
         }
         __syncthreads();
         if (j < n) {
