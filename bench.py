@@ -272,6 +272,9 @@ def serve_leg(count, warm):
             "service_p99_ms": round(float(np.percentile(svc, 99)), 3),
             "converged": ok, "measured": len(meas),
             "ingest_ms_mean": round(float(np.mean([r["ms_ingest"] for r, _ in meas])), 3),
+            "phase_ms_mean": {k: round(float(np.mean([r["ms_" + k] for r, _ in meas])), 3)
+                              for k in ("sketch", "factor", "refine")},
+            "inner_iters_mean": round(float(np.mean([r["inner_iters"] for r, _ in meas])), 1),
             "saturation_solves_per_s": round(nsat / (t1 - t0), 2),
             "hbm_high_water_GiB": round(stats["bytes_high_water"] / 2 ** 30, 3),
             "budget_GiB": round(stats["budget"] / 2 ** 30, 3),

@@ -106,6 +106,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsketch.so is not built; run python -m paper_2606_20195_amd.build "
                           "(expected at %s)" % LIB_PATH)
+    # The library binds to the HIP runtime already in the process.  PyTorch
+    # ships its own copy of that runtime; loading torch first makes both use
+    # the same one (loaded the other way round, torch would find no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     sig = {

@@ -49,6 +49,7 @@ struct SolveState {
     double rel;         // ||r|| / ||b||
     double alpha, rhobar, phibar, anorm2, coef, beta1;
     double alpha1;      // ||(A P)^T r/||r|| || at the start of the current LSQR run
+    double rfro2;       // ||R||_F^2 of the triangular factor of the sketch
     double tol, inner_tol;
     int32_t outer_done, inner_done, inner_iter, total_inner;
     int32_t bad, max_inner, pad0, pad1;
@@ -288,16 +289,23 @@ __device__ void matvec_cols(const float* S, int64_t lds_, int n, const double* i
 }
 
 // True in exactly one workgroup, the last to finish; partials written before
-// the call are visible to it.
+// the call are visible to it.  Each wave first waits for its own stores to be
+// acknowledged; after the barrier one thread takes a ticket with an
+// agent-scope release add, so each workgroup writes its XCD's L2 back once (a
+// fence in every wave would write back and invalidate the L2 once per wave,
+// which also evicts the data of kernels running beside this one).  Only the
+// last workgroup then invalidates (acquire fence after the add that read the
+// final count), to read the other XCDs' partials.
 __device__ bool last_workgroup(uint32_t* ticket)
 {
     __shared__ int last;
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
     __syncthreads();
     if (!last) return false;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (threadIdx.x == 0) *ticket = 0u;
     return true;
 }
@@ -688,8 +696,16 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
     // test is relative to the start, not to ||r^||: near the solution r^ is
     // almost orthogonal to the range of A, and a test relative to ||r^|| would
     // stop after one iteration.
+    //   It also stops once the same estimate bounds the outer criterion below
+    // half its tolerance: with A = (A P) R, the updated residual r' satisfies
+    // ||A^T r'|| <= ||R||_2 ||(A P)^T r'||, and ||r'|| = phibar ||r||, so
+    // ||A^T r'|| / (||A||_F ||r'||) <= (||R||_F / ||A||_F) alpha |c|.  The
+    // estimate holds until FP32 rounding in the products dominates; the FP64
+    // residual of the next outer step decides convergence either way.
     const double test2 = st->alpha1 > 0.0 ? phibar * alpha * fabs(c) / st->alpha1 : 0.0;
-    const bool done = beta == 0.0 || alpha == 0.0 || test2 <= itol || phibar <= itol || iter >= st->max_inner;
+    const double crit_est = st->fro2 > 0.0 ? sqrt(st->rfro2 / st->fro2) * alpha * fabs(c) : 1.0;
+    const bool done = beta == 0.0 || alpha == 0.0 || test2 <= itol || phibar <= itol || crit_est <= 0.5 * st->tol ||
+                      iter >= st->max_inner;
     const double scale = st->beta1;
     for (int j = tid; j < n; j += kT) {
         const double tn = (mg[j] - beta * p.tv[j]) * ia;      // P v_{k+1}
@@ -908,14 +924,17 @@ __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, i
 }
 
 // P = R^-1 (and P^T) by back substitution: wave w of workgroup b computes
-// column j = 16 b + w; rows of R are staged through LDS 16 at a time.
+// column j = 16 b + w; rows of R are staged through LDS 16 at a time.  The
+// last workgroup stages all of R; if rfro2 is given it stores ||R||_F^2 there.
 __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, int32_t n, float* P, float* PT,
-                                                    int64_t ldp, int32_t* bad)
+                                                    int64_t ldp, int32_t* bad, double* rfro2)
 {
     extern __shared__ float rp[];        // [16][J]
+    __shared__ double red[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = blockIdx.x * kWaves + wave;
     const int J = min(n, (int)(blockIdx.x + 1) * kWaves);
+    double sq = 0.0;                     // squares of the staged entries (all of R in the last workgroup)
     float xv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) xv[q] = 0.0f;
@@ -937,6 +956,7 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
             for (int e = 0; e < 8; ++e) {
                 const int idx = base + e * kT + tid;
                 if (idx < cnt) rp[idx] = v[e];
+                sq = fma((double)v[e], (double)v[e], sq);
             }
         }
         __syncthreads();
@@ -970,6 +990,10 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
             PT[(int64_t)j * ldp + i] = val;
         }
         if (!ok && lane == 0) *bad = 1;
+    }
+    if (rfro2 && blockIdx.x == gridDim.x - 1) {
+        const double t = block_sum(sq, red);
+        if (tid == 0) *rfro2 = t;
     }
 }
 
@@ -1083,13 +1107,13 @@ hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
 }
 
 hipError_t run_trinv(const float* R, int64_t ldr, int64_t n, float* P, float* PT, int64_t ldp, int32_t* bad,
-                     hipStream_t st)
+                     double* rfro2, hipStream_t st)
 {
     const int64_t grid = (n + kWaves - 1) / kWaves;
     const size_t lds = (size_t)16 * std::min<int64_t>(n, grid * kWaves) * 4;
     hipError_t e = set_lds((const void*)trinv_kernel, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(trinv_kernel, dim3((unsigned)grid), dim3(kT), lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad);
+    hipLaunchKernelGGL(trinv_kernel, dim3((unsigned)grid), dim3(kT), lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2);
     return hipGetLastError();
 }
 
@@ -1427,7 +1451,7 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
 
     // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
     if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
-    if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.M, (float*)ra.PT, n, &ra.st->bad, st)) != hipSuccess)
+    if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.M, (float*)ra.PT, n, &ra.st->bad, &ra.st->rfro2, st)) != hipSuccess)
         return job_fail(j, hip_err(e, "inverse kernel"));
     hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st,
                        ra.PT, (int64_t)n, (int32_t)n, (float*)ra.M);
@@ -1572,7 +1596,7 @@ int sketch_trinv_f32(const float* R, int64_t n, int64_t ldr, float* P, float* PT
 {
     if (!R || !P || !PT || !bad) return set_error(SK_EINVAL, "NULL argument");
     if (n < 1 || n > kMaxN || ldr < n || ldp < n) return set_error(SK_EINVAL, "bad shape n=%lld", (long long)n);
-    hipError_t e = run_trinv(R, ldr, n, P, PT, ldp, bad, (hipStream_t)stream);
+    hipError_t e = run_trinv(R, ldr, n, P, PT, ldp, bad, nullptr, (hipStream_t)stream);
     return e == hipSuccess ? SK_OK : hip_err(e, "inverse kernel");
 }
 
