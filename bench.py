@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--serve", type=int, default=2000, help="measured requests of the serving leg at 200 req/s "
                    "(after a tenth as many warm-up requests); 0 = skip the leg")
     p.add_argument("--profile-run", action="store_true", help="short fixed sequence for counter passes")
+    p.add_argument("--no-paper-scheme", action="store_true",
+                   help="skip timing the one-atomic-per-contribution scheme against the partial-sum kernels")
     return p.parse_args()
 
 
@@ -284,6 +286,53 @@ def serve_leg(count, warm):
     return out
 
 
+def paper_scheme_leg(A, stream):
+    """The paper's own kernel scheme (one global atomic per contribution,
+    Sections 4.1-4.2) against the workgroup-partial kernels on the headline
+    input: kernel time, global atomic count and error against an FP64
+    reference, per rounding rule.  The reference is a plain PyTorch FP64
+    scatter (index_add_) over the library's row hash, which the tests hold
+    bit-exact to the oracle's."""
+    import torch
+    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
+    buckets, signs = Sketch(M, D, S, 0).hash(0, M)
+    A64 = A.double()
+    ref_t = torch.zeros((D, N), dtype=torch.float64, device=A.device)
+    for j in range(S):
+        ref_t.index_add_(0, buckets[:, j].long(), A64 * (signs[:, j].double() / np.sqrt(S))[:, None])
+    ref = ref_t.cpu().numpy()
+    del A64, ref_t, buckets, signs
+    torch.cuda.empty_cache()
+    nref = float(np.linalg.norm(ref))
+    out = {"workload": "A 4194304x64 FP16 (the headline input), d=1024, s=4; error = ||SA - SA_fp64||_F / "
+                       "||SA_fp64||_F, SA_fp64 from a torch FP64 index_add_ over the row hash",
+           "per_contribution_atomics": {"fp32": M * S * N, "fp16": M * S * ((N + 1) // 2)}}
+    for name, code in (("fp16_rn", ACC_F16_RN), ("fp16_sr", ACC_F16_SR), ("fp16_dither", ACC_F16_DITHER),
+                       ("fp32", ACC_F32)):
+        row = {}
+        for scheme in ("per_contribution", "partials"):
+            sk = Sketch(M, D, S, 0, code)
+            if scheme == "per_contribution":
+                sk.set_schedule(per_contribution=1)
+            SA = sk.apply(A, epoch=1)
+            torch.cuda.synchronize()
+            err = float(np.linalg.norm(SA.double().cpu().numpy() - ref)) / nref
+            per = time_calls(lambda: sk.apply(A, SA=SA, accumulate=True), 3 if scheme == "per_contribution" else 20,
+                             stream)
+            kms = float(np.mean(per))
+            plan = sk.plan(1, M, N)
+            if scheme == "partials":
+                units = -(-M // plan["chunk_rows"])
+                atomics = units * D * (N if code == ACC_F32 else (N + 1) // 2)
+            else:
+                atomics = M * S * (N if code == ACC_F32 else (N + 1) // 2)
+            row[scheme] = {"kernel_ms": round(kms, 4), "GB/s": round((M * N * 2) / (kms * 1e-3) / 1e9, 1),
+                           "global_atomics": atomics, "rel_err": float("%.4g" % err)}
+            del SA
+        out[name] = row
+    return out
+
+
 def profile_run():
     """Fixed short sequence for rocprofv3 counter passes."""
     import torch
@@ -365,6 +414,7 @@ def main():
                                   "GB/s": round((M * N * 4 + D * N * 4) / (k32 * 1e-3) / 1e9, 1)}
         del A32
 
+    paper = None if args.no_paper_scheme else paper_scheme_leg(A, stream)
     del A
     torch.cuda.empty_cache()
     batch = None if args.no_batch else batch_leg()
@@ -396,6 +446,8 @@ def main():
                      "algorithmic_bytes": alg_bytes},
         "modes": modes,
     }
+    if paper is not None:
+        line["paper_scheme"] = paper
     if batch is not None:
         line["batch"] = batch
     if ls is not None:

@@ -76,8 +76,23 @@ typedef struct sk_schedule {
     int32_t block_group;  /* blocks per workgroup: 1, 2, 4 or 8, dividing s   */
     int32_t waves;        /* waves (64 lanes) per workgroup: 4, 8 or 16       */
     int32_t xcd_remap;    /* 1: place all tiles of a unit on one XCD; 0: off  */
-    int32_t reserved[4];  /* must be zero                                     */
+    int32_t per_contribution; /* 1: the paper's kernel scheme, see below      */
+    int32_t reserved[3];  /* must be zero                                     */
 } sk_schedule;
+
+/*
+ * per_contribution = 1 replaces the workgroup partials by one global atomic
+ * per contribution, the scheme of the paper's Section 4 kernels: for every
+ * row i, block j and column c the FP32 value fl32(rho_ij * fl32(1/sqrt(s)) *
+ * A[i][c]) is added to SA[b_ij][c] -- in FP32 mode with an FP32 atomic
+ * (Section 4.1), in the FP16 modes after rounding it to FP16 with the
+ * handle's rule and with packed FP16 atomics on column pairs (Section 4.2),
+ * so m*n*s values are rounded and summed in FP16 in an unspecified order.
+ * SR and dither take site q = (i*s + j)*n + c of the rounding stream.  The
+ * other schedule fields are ignored; single sketches only (not batches).
+ * It is a reference for accuracy and atomic counts, far slower than the
+ * partial-sum scheme, and the planner never picks it.
+ */
 
 /*
  * sketch_create -- describe S (d x m) once.

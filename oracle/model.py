@@ -117,3 +117,68 @@ def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=No
         qv = quantize(mode, v, u)
         acc = f16_add(acc, qv)
     return acc
+
+
+def contribution_sites(rows, j, n, s):
+    """Rounding-noise sites of the per-contribution scheme: q = (i*s + j)*n + c
+    for global rows i (array), block j and every column c."""
+    rows = np.asarray(rows, dtype=np.uint64)
+    return ((rows[:, None] * np.uint64(s) + np.uint64(j)) * np.uint64(n)
+            + np.arange(n, dtype=np.uint64)[None, :])
+
+
+def apply_per_contribution_model(A, d, s, seed, mode, epoch=0, row_offset=0, SA0=None):
+    """The paper's own kernel scheme (Section 4.1 scatter; Section 4.2
+    quantise-then-add), rows taken in order.
+
+    Every contribution is the FP32 product v = fl32(sv * x) of the stored S
+    value sv = +-fl32(1/sqrt(s)) and the element x.  mode 0 (FP32 output):
+    SA[b, c] += v in FP32.  Modes 1..3 (FP16 output): v is rounded to FP16
+    with the rule (noise from site q = (i*s + j)*n + c of the rounding
+    stream) and added with an FP16 round-to-nearest addition.  The GPU adds
+    in an unspecified order, so the two agree exactly only where every sum is
+    exact or each entry receives one contribution.
+
+    Zero contributions: each rule maps +-0 to a zero (dither's exact FMA
+    t*(x*2^-10) + x gives -0 only for x = -0 and t >= 0), and adding a zero
+    to an FP16 sum changes it only if the sum is -0; a sum that starts
+    without -0 never becomes -0 under round-to-nearest additions, so rows
+    whose contributions are all zero are skipped (SA0 must hold no -0).
+    """
+    from .sketch import hash_rows
+    check_shape(d, s)
+    A = np.asarray(A)
+    m, n = A.shape
+    f16 = mode != ACC_F32
+    dt = np.float16 if f16 else np.float32
+    acc = np.zeros((d, n), dtype=dt) if SA0 is None else np.asarray(SA0, dtype=dt).copy()
+    if np.any((acc == 0) & np.signbit(acc)):
+        raise ValueError("SA0 holds -0")
+    rows = np.arange(m, dtype=np.uint64) + np.uint64(row_offset)
+    buckets, signs = hash_rows(seed, rows, d, s)
+    cs = c_s32(s)
+    x32 = A.astype(np.float32)
+    for j in range(s):
+        sv = np.where(signs[:, j] < 0, -cs, cs).astype(np.float32)
+        v = (sv[:, None] * x32).astype(np.float32)               # [m, n], one FP32 product each
+        if f16:
+            u = None
+            if mode in (ACC_F16_SR, ACC_F16_DITHER):
+                u = round_u24(seed, epoch, contribution_sites(rows, j, n, s))
+            qv = np.zeros(v.shape, dtype=np.float16)
+            nz = v != 0
+            qv[nz] = quantize(mode, v[nz], None if u is None else u[nz])
+            zs = np.signbit(v) & ~nz
+            if mode == ACC_F16_DITHER:
+                zs &= u >= np.uint64(1 << 23)
+            qv[zs] = np.float16(-0.0)
+        else:
+            qv = v
+        b = buckets[:, j]
+        live = np.nonzero(np.any(qv != 0, axis=1))[0]
+        for i in live:
+            if f16:
+                acc[b[i]] = f16_add(acc[b[i]], qv[i])
+            else:
+                acc[b[i]] = (acc[b[i]] + qv[i]).astype(np.float32)
+    return acc

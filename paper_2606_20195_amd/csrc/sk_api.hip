@@ -79,6 +79,12 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
     }
     const int64_t W = h->d / h->s;
     const sk_schedule* f = h->forced ? &h->sched : nullptr;
+    if (f && f->per_contribution) {
+        Plan pl;
+        pl.direct = true;
+        *out = pl;
+        return SK_OK;
+    }
     const bool dual = h->rounding == SK_ACC_F32;   // FP32 mode keeps two fields per element
     Plan pl;
     // blocks per workgroup
@@ -142,7 +148,9 @@ static int check_schedule(const sk_schedule* s)
     if (s->waves && s->waves != 4 && s->waves != 8 && s->waves != 16)
         return set_error(SK_EINVAL, "waves must be 0, 4, 8 or 16");
     if (s->xcd_remap != 0 && s->xcd_remap != 1) return set_error(SK_EINVAL, "xcd_remap must be 0 or 1");
-    for (int i = 0; i < 4; ++i)
+    if (s->per_contribution != 0 && s->per_contribution != 1)
+        return set_error(SK_EINVAL, "per_contribution must be 0 or 1");
+    for (int i = 0; i < 3; ++i)
         if (s->reserved[i]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     return SK_OK;
 }
@@ -220,6 +228,7 @@ int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedu
     out->block_group = pl.bg;
     out->waves = pl.waves;
     out->xcd_remap = pl.xcd_remap;
+    out->per_contribution = pl.direct ? 1 : 0;
     return SK_OK;
 }
 
@@ -278,6 +287,19 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     a.aligned = (n % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % vec_align == 0);
     const float cs = value_scale32(h->s);
 
+    if (pl.direct) {
+        // one global atomic per contribution (the paper's kernel scheme)
+        if (!accumulate) {
+            if ((e = launch_fill(SA, f16 ? 2 : 4, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");
+        }
+        if (rows == 0) return SK_OK;
+        a.SA = SA;
+        a.ldsa = ldsa;
+        a.mode = f16 ? h->rounding : 0;
+        a.scale = cs;
+        if ((e = launch_contrib(a_dtype, a, st)) != hipSuccess) return hip_fail(e, "per-contribution kernel");
+        return SK_OK;
+    }
     if (f16) {
         if (!accumulate) {
             if ((e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");

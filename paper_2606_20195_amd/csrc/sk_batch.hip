@@ -272,7 +272,9 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
             return set_error(SK_EINVAL, "block_group must be 0, 1, 2, 4 or 8");
         if (sched->waves && sched->waves != 4 && sched->waves != 8 && sched->waves != 16)
             return set_error(SK_EINVAL, "waves must be 0, 4, 8 or 16");
-        for (int i = 0; i < 4; ++i)
+        if (sched->per_contribution)
+            return set_error(SK_EUNSUPPORTED, "per-contribution schedules apply to single sketches only");
+        for (int i = 0; i < 3; ++i)
             if (sched->reserved[i]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     }
     int rc;

@@ -50,7 +50,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 
 __device__ __forceinline__ uint32_t word_of(const uint4& w, uint32_t i)
 {
-    return i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w;
+    // three selects on the bits of i (a per-lane index must not become a branch)
+    const uint32_t a = (i & 1u) ? w.y : w.x;
+    const uint32_t b = (i & 1u) ? w.w : w.z;
+    return (i & 2u) ? b : a;
 }
 
 // Hash words of row i, Philox call g (blocks 4g .. 4g+3).

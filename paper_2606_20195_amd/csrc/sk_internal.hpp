@@ -45,6 +45,7 @@ struct Plan {
     int64_t units = 0;
     int32_t xcd_remap = 0;
     size_t lds_bytes = 0;
+    bool direct = false;     // one global atomic per contribution
 };
 
 size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual);
@@ -77,6 +78,8 @@ struct BatchDesc {
 };
 
 hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
+// One global atomic per contribution (args.mode: 0 FP32 SA, 1..3 FP16 SA).
+hipError_t launch_contrib(int a_dtype, const ApplyArgs &args, hipStream_t st);
 // Clear all SAs, one persistent apply over all problems, FP32 epilogue scale if needed.
 hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count,
                           int64_t total_items, uint32_t *counter, int grid, int waves, size_t lds_bytes,

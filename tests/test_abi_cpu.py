@@ -200,3 +200,13 @@ def test_tuning_file_roundtrip(lib, tmp_path):
     assert lib.sketch_load_tuning(str(tmp_path / "missing.json").encode()) == _lib.EINVAL
     assert lib.sketch_load_tuning(None) == _lib.EINVAL
     assert lib.sketch_clear_tuning() == 0
+
+
+def test_per_contribution_schedule_validation():
+    from paper_2606_20195_amd import ACC_F16_RN, SketchError, Sketch
+    sk = Sketch(1000, 64, 4, 1, ACC_F16_RN)
+    with pytest.raises(SketchError) as ei:
+        sk.set_schedule(per_contribution=2)
+    assert ei.value.code == -1
+    sk.set_schedule(per_contribution=1)
+    sk.clear_schedule()
