@@ -128,9 +128,14 @@ int sketch_destroy(sk_handle h);
  * FP32 mode: SA = fl32(fl32(1/sqrt(s)) * sum) with the sum accumulated in
  * FP32 in an unspecified order (exact for integer-valued A whose partial sums
  * stay below 2^24).  FP16 modes: see sk_schedule.
+ * When d/s bucket rows of 32 FP32 values do not fit in LDS (d/s above about
+ * 1200), the whole call is one unit: its unscaled contributions are summed
+ * with FP32 atomics in a d x n FP32 workspace that the handle allocates on
+ * first need and keeps, then scaled and (FP16 modes) rounded once per entry
+ * at sites q = row_offset*d*n + b*n + c.  That path is much slower.
  * The call enqueues work on `stream` and returns; it does not synchronise.
- * Errors: SK_EINVAL (shapes, pointers, flags), SK_EUNSUPPORTED (alignment,
- * d too large for any schedule), SK_ENOMEM, SK_EHIP.
+ * Errors: SK_EINVAL (shapes, pointers, flags), SK_EUNSUPPORTED (alignment, a
+ * forced block_group that does not fit), SK_ENOMEM, SK_EHIP.
  */
 int sketch_apply(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int64_t n,
                  int64_t lda, int64_t row_offset, void *SA, int64_t ldsa, uint32_t flags,
@@ -145,7 +150,8 @@ int sketch_set_schedule(sk_handle h, const sk_schedule *sched);
 
 /*
  * sketch_plan -- the schedule sketch_apply would use for (a_dtype, rows, n)
- * on this handle and the current device, written to *out.  Errors:
+ * on this handle and the current device, written to *out (all fields zero
+ * for the workspace path of large d/s, see sketch_apply).  Errors:
  * SK_EINVAL, SK_EUNSUPPORTED, SK_EHIP (device query).
  */
 int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedule *out);

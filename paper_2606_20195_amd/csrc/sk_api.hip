@@ -101,9 +101,13 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
                 break;
             }
         }
-        if (!pl.bg)
-            return set_error(SK_EUNSUPPORTED, "d/s = %lld bucket rows of 32 FP32 values exceed the %zu B of LDS",
-                             (long long)W, dev.lds_max);
+        if (!pl.bg) {
+            // no block fits in LDS: FP32 workspace path (sketch_apply)
+            Plan g;
+            g.global = true;
+            *out = g;
+            return SK_OK;
+        }
     }
     pl.lds_bytes = apply_lds_bytes(pl.bg, W, dual);
     pl.bgroups = h->s / pl.bg;
@@ -287,6 +291,43 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     a.aligned = (n % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % vec_align == 0);
     const float cs = value_scale32(h->s);
 
+    // d x n FP32 workspace held by the handle (allocated on first need)
+    auto ensure_ws = [&](size_t need) -> int {
+        if (h->ws_floats >= need) return SK_OK;
+        if (h->ws) (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_floats = 0;
+        if ((e = hipMalloc((void**)&h->ws, need * sizeof(float))) != hipSuccess)
+            return set_error(SK_ENOMEM, "workspace of %zu floats: %s", need, hipGetErrorString(e));
+        h->ws_floats = need;
+        return SK_OK;
+    };
+    if (pl.global) {
+        // d/s bucket rows beyond LDS: the whole call is one unit, summed
+        // unscaled in an FP32 workspace with FP32 atomics, then finished once.
+        if (rows == 0) {
+            if (!accumulate && (e = launch_fill(SA, f16 ? 2 : 4, h->d, n, ldsa, st)) != hipSuccess)
+                return hip_fail(e, "fill SA");
+            return SK_OK;
+        }
+        if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
+        if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+        a.SA = h->ws;
+        a.ldsa = n;
+        a.mode = 0;
+        a.scale = 1.0f;
+        if ((e = launch_contrib(a_dtype, a, st)) != hipSuccess) return hip_fail(e, "workspace kernel");
+        if (f16) {
+            if (!accumulate && (e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess)
+                return hip_fail(e, "fill SA");
+            e = launch_finish16(h->ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
+                                (uint64_t)row_offset * (uint64_t)h->d * (uint64_t)n, round_epoch, a.k0, a.k1, st);
+            if (e != hipSuccess) return hip_fail(e, "finish kernel");
+        } else if ((e = launch_scale((float*)SA, h->d, n, ldsa, h->ws, cs, accumulate ? 1 : 0, st)) != hipSuccess) {
+            return hip_fail(e, "scale kernel");
+        }
+        return SK_OK;
+    }
     if (pl.direct) {
         // one global atomic per contribution (the paper's kernel scheme)
         if (!accumulate) {
@@ -333,15 +374,7 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     // Accumulating with a non-power-of-two scale: sum into a workspace, then
     // SA += fl32(c_s * sum).
     if (rows == 0) return SK_OK;
-    const size_t need = (size_t)h->d * (size_t)n;
-    if (h->ws_floats < need) {
-        if (h->ws) (void)hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_floats = 0;
-        if ((e = hipMalloc((void**)&h->ws, need * sizeof(float))) != hipSuccess)
-            return set_error(SK_ENOMEM, "workspace of %zu floats: %s", need, hipGetErrorString(e));
-        h->ws_floats = need;
-    }
+    if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
     if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
     a.SA = h->ws;
     a.ldsa = n;

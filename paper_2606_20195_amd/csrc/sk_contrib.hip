@@ -72,6 +72,36 @@ __global__ __launch_bounds__(kContribThreads) void contrib_kernel(ApplyArgs p)
     }
 }
 
+// FP16 finish of the workspace path: SA[b][c] += RN16-add of the rounding of
+// fl32(scale * ws[b][c]), one rounding per entry at site q = site0 + b*n + c
+// (the partial-sum scheme's rule for a unit that starts at global row
+// site0 / (d*n) and spans the whole call).
+__global__ __launch_bounds__(kContribThreads) void finish16_kernel(const float* ws, int64_t d, int32_t n,
+                                                                   uint16_t* SA, int64_t ldsa, int32_t mode,
+                                                                   float scale, uint64_t site0, uint32_t epoch,
+                                                                   uint32_t k0, uint32_t k1)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const int64_t npairs = (n + 1) / 2;
+    const int64_t total = d * npairs;
+    for (int64_t e = (int64_t)blockIdx.x * kContribThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kContribThreads) {
+        const int64_t b = e / npairs;
+        const int c = 2 * (int)(e - b * npairs);
+        const bool two = c + 1 < n;
+        const uint64_t q = site0 + (uint64_t)b * (uint64_t)n + (uint64_t)c;
+        uint32_t u0 = 0, u1 = 0;
+        if (mode >= 2) {
+            u0 = round_bits(q, epoch, k0, k1);
+            u1 = round_bits(q + 1, epoch, k0, k1);
+        }
+        const uint16_t h0 = quantize(mode, ws[b * n + c] * scale, u0);
+        const uint16_t h1 = two ? quantize(mode, ws[b * n + c + 1] * scale, u1) : (uint16_t)0x8000u;
+        const h2 hv = __builtin_bit_cast(h2, (uint32_t)h0 | ((uint32_t)h1 << 16));
+        __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * ldsa + c), hv);
+    }
+}
+
 template <typename AT>
 hipError_t contrib_typed(const ApplyArgs& a, hipStream_t st)
 {
@@ -87,6 +117,17 @@ hipError_t contrib_typed(const ApplyArgs& a, hipStream_t st)
 }
 
 }  // namespace
+
+hipError_t launch_finish16(const float* ws, int64_t d, int32_t n, uint16_t* SA, int64_t ldsa, int32_t mode,
+                           float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, hipStream_t st)
+{
+    const int64_t total = d * ((n + 1) / 2);
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + kContribThreads - 1) / kContribThreads;
+    hipLaunchKernelGGL(finish16_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(kContribThreads), 0,
+                       st, ws, d, n, SA, ldsa, mode, scale, site0, epoch, k0, k1);
+    return hipGetLastError();
+}
 
 hipError_t launch_contrib(int a_dtype, const ApplyArgs& a, hipStream_t st)
 {

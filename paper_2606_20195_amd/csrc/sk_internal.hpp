@@ -46,6 +46,7 @@ struct Plan {
     int32_t xcd_remap = 0;
     size_t lds_bytes = 0;
     bool direct = false;     // one global atomic per contribution
+    bool global = false;     // d/s too large for LDS partials: FP32 workspace of the whole call
 };
 
 size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual);
@@ -80,6 +81,9 @@ struct BatchDesc {
 hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
 // One global atomic per contribution (args.mode: 0 FP32 SA, 1..3 FP16 SA).
 hipError_t launch_contrib(int a_dtype, const ApplyArgs &args, hipStream_t st);
+// SA (FP16, ld ldsa) += rounding of fl32(scale * ws) per entry, sites site0 + b*n + c.
+hipError_t launch_finish16(const float *ws, int64_t d, int32_t n, uint16_t *SA, int64_t ldsa, int32_t mode,
+                           float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, hipStream_t st);
 // Clear all SAs, one persistent apply over all problems, FP32 epilogue scale if needed.
 hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count,
                           int64_t total_items, uint32_t *counter, int grid, int waves, size_t lds_bytes,

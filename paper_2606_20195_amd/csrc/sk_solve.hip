@@ -1192,7 +1192,7 @@ hipError_t launch_rows(int a_dtype, bool resid, const Geo& g, const RowArgs& a, 
 // end; the request server keeps one job per slot and interleaves them.
 struct SolveJob {
     // problem
-    sk_sketch S;                 // the S of A (no workspace of its own)
+    sk_sketch S;                 // the S of A (its large-d/s workspace is the job's own)
     sk_sketch Sb;                // the same S in FP32 mode, for b
     const void* A = nullptr;
     int32_t a_dtype = 0;
@@ -1238,6 +1238,7 @@ void job_delete(SolveJob* j)
         if (e) (void)hipEventDestroy(e);
     if (j->ev_state) (void)hipEventDestroy(j->ev_state);
     if (j->Sb.ws) (void)hipFree(j->Sb.ws);
+    if (j->S.ws) (void)hipFree(j->S.ws);       // the job's own (large d/s sketches)
     delete j;
 }
 
@@ -1277,9 +1278,11 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     const int64_t rpw = (m + nwg0 - 1) / nwg0;
     if (rpw * lda * esz >= ((int64_t)1 << 31))
         return set_error(SK_EUNSUPPORTED, "rows per workgroup span more than 2 GiB");
+    float* own_ws = j->S.ws;                    // kept across prepares of this job
+    const size_t own_floats = j->S.ws_floats;
     j->S = S;
-    j->S.ws = nullptr;
-    j->S.ws_floats = 0;
+    j->S.ws = own_ws;                            // never the caller's handle workspace
+    j->S.ws_floats = own_floats;
     j->S.sw = nullptr;
     if (j->Sb.ws) (void)hipFree(j->Sb.ws);
     j->Sb = sk_sketch{};
@@ -1334,7 +1337,15 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     ra.ldp = n;
     ra.pst = pst;
     j->phase = 0;
-    *footprint = j->total;
+    // Sketches whose d/s rows do not fit in LDS sum in a d x n FP32
+    // workspace that sketch_apply allocates beside the job's block; count it
+    // (and b's d x 1 one) so admission by footprint stays honest.
+    size_t extra = 0;
+    Plan pa, pb;
+    if (make_plan(&j->S, a_dtype, m, n, lda, dev, &pa) == SK_OK && pa.global) extra += (size_t)S.d * n * 4;
+    if (make_plan(&j->Sb, SK_F32, m, 1, 1, dev, &pb) == SK_OK && pb.global) extra += (size_t)S.d * 4;
+    set_error(SK_OK, "");
+    *footprint = j->total + extra;
     return SK_OK;
 }
 

@@ -219,3 +219,45 @@ def test_full_size_coherent_and_spikes_fp16():
             got = run(to_dev(A), A.shape[0], 1024, s, 0, ACC_F16_RN)
             ref = native.sketch_f64(A, 1024, s, 0)
             assert rel_fro(got, ref) <= 4e-3, (kind, s)
+
+
+# ---- d/s beyond the LDS partials: the FP32 workspace path (one unit per call)
+
+def test_large_bucket_count_plans_the_workspace():
+    sk = Sketch(100000, 4096, 1, 3, ACC_F16_RN)
+    assert sk.plan(1, 100000, 64)["block_group"] == 0
+    assert Sketch(100000, 1024, 4, 3, ACC_F16_RN).plan(1, 100000, 64)["block_group"] > 0
+
+
+@pytest.mark.parametrize("d,s,n", [(4096, 1, 32), (16384, 4, 17), (6000, 3, 40)])
+def test_workspace_path_fp32_integer_is_bit_exact(d, s, n):
+    A = workloads.integers(30000, n, seed=51, lim=6)
+    got = run(to_dev(A), 30000, d, s, 12, ACC_F32)
+    assert np.array_equal(got, model.apply_f32_exact_int(A, d, s, 12))
+
+
+@pytest.mark.parametrize("rounding", [ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER])
+def test_workspace_path_fp16_integer_is_one_unit(rounding):
+    d, s, m, n = 8192, 2, 20000, 24
+    A = workloads.integers(m, n, seed=52, lim=5).astype(np.float16)
+    sk = Sketch(m + 500, d, s, 13, rounding)
+    SA = torch.zeros((d, n), dtype=torch.float16, device="cuda")
+    sk.apply(to_dev(A), SA=SA, row_offset=500, epoch=6)
+    torch.cuda.synchronize()
+    ref = model.apply_f16_model(A, d, s, 13, rounding, 6, chunk_rows=m, row_offset=500)
+    assert np.array_equal(SA.cpu().numpy().view(np.uint16), ref.view(np.uint16))
+
+
+def test_workspace_path_gaussian_tolerances_and_accumulate():
+    d, s, m, n = 16384, 4, 60000, 32
+    A = workloads.gaussian(m, n, 53, np.float16)
+    ref = apply_f64(A, d, s, 14)
+    got16 = run(to_dev(A), m, d, s, 14, ACC_F16_SR, epoch=2)
+    assert rel_fro(got16, ref) <= 4e-3
+    # two row shards accumulated equal one call in FP32 mode, to FP32 rounding
+    sk = Sketch(m, d, s, 14, ACC_F32)
+    Ad = to_dev(A)
+    SA = sk.apply(Ad[:25000])
+    sk.apply(Ad[25000:], SA=SA, row_offset=25000, accumulate=True)
+    torch.cuda.synchronize()
+    assert rel_fro(SA.cpu().numpy(), ref) <= 1e-5

@@ -234,3 +234,15 @@ def test_solve_full_size_coherent_fp16():
     assert crit <= 1.5e-10, crit
     x_opt = native.lstsq(A, b)
     assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
+
+
+def test_solve_with_a_workspace_sketch():
+    # d/s = 2400 bucket rows: the sketch takes the FP32 workspace path
+    m, n, d = 60000, 300, 2400
+    A = workloads.gaussian(m, n, 71, np.float16)
+    b = A.astype(np.float64) @ workloads.rng(72).standard_normal(n) + 1e-6 * workloads.rng(73).standard_normal(m)
+    sk = Sketch(m, d, 1, 5, ACC_F16_RN)
+    assert sk.plan(1, m, n)["block_group"] == 0
+    x, info = sk.solve(torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda())
+    assert info["converged"] == 1
+    assert ne_criterion(A, b, x.cpu().numpy()) <= 1.5e-10
