@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--serve", type=int, default=2000, help="measured requests of the serving leg at 200 req/s "
                    "(after a tenth as many warm-up requests); 0 = skip the leg")
     p.add_argument("--profile-run", action="store_true", help="short fixed sequence for counter passes")
+    p.add_argument("--coherence", action="store_true",
+                   help="run only the coherence sweep (eta against mu(U)) and print its JSON line")
     p.add_argument("--no-paper-scheme", action="store_true",
                    help="skip timing the one-atomic-per-contribution scheme against the partial-sum kernels")
     return p.parse_args()
@@ -333,6 +335,69 @@ def paper_scheme_leg(A, stream):
     return out
 
 
+def eta_of(SU):
+    """eta(S, U) = max(|sigma_max - 1|, |1 - sigma_min|) of a d x n sketch,
+    from the eigenvalues of its FP64 Gram matrix (Section 2, the subspace
+    embedding distortion)."""
+    import torch
+    X = SU.double()
+    ev = torch.linalg.eigvalsh(X.T @ X).clamp_min(0).sqrt()
+    return float(max(abs(ev[-1].item() - 1.0), abs(1.0 - ev[0].item())))
+
+
+def coherence_leg(m=1 << 21, n=1024, alphas=(0.0, 0.3, 0.5, 0.7, 0.85, 0.95, 0.99, 1.0), ratios=(2, 4, 8, 16),
+                  svals=(1, 4), seed=0):
+    """The paper's coherence sweep (Section 5, coherence sweep): U(alpha) =
+    orth((1 - alpha) Q_rand + alpha [I_n; 0]) with Q_rand the orthogonal factor
+    of an m x n Gaussian, coherence mu(U) = (m/n) max_i ||U_i||^2, and the
+    distortion eta of S U for s in {1 (CountSketch), 4} and every rounding
+    mode.  U is formed in FP64 (Householder QR on the device) and stored as
+    FP32; eta_fp64 sketches that stored U in FP64 (torch index_add_ over the
+    library's row hash, the same S)."""
+    import torch
+    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    G = torch.randn((m, n), dtype=torch.float64, device=dev, generator=gen)
+    Qr = torch.linalg.qr(G)[0]
+    del G
+    modes = (("fp32", ACC_F32), ("fp16_rn", ACC_F16_RN), ("fp16_sr", ACC_F16_SR), ("fp16_dither", ACC_F16_DITHER))
+    rows = []
+    for a in alphas:
+        Mx = (1.0 - a) * Qr
+        Mx[:n] += a * torch.eye(n, dtype=torch.float64, device=dev)
+        U = torch.linalg.qr(Mx)[0]
+        del Mx
+        mu = float((m / n) * (U * U).sum(dim=1).max().item())
+        U32 = U.float().contiguous()
+        del U
+        U64 = U32.double()
+        torch.cuda.empty_cache()
+        for r in ratios:
+            d = r * n
+            for s in svals:
+                buckets, signs = Sketch(m, d, s, seed).hash(0, m)
+                ref = torch.zeros((d, n), dtype=torch.float64, device=dev)
+                for j in range(s):
+                    ref.index_add_(0, buckets[:, j].long(), U64 * (signs[:, j].double() / np.sqrt(s))[:, None])
+                del buckets, signs
+                row = {"alpha": a, "mu": round(mu, 2), "d_over_n": r, "s": s, "eta_fp64": round(eta_of(ref), 5)}
+                del ref
+                for name, code in modes:
+                    SA = Sketch(m, d, s, seed, code).apply(U32)
+                    torch.cuda.synchronize()
+                    row["eta_" + name] = round(eta_of(SA), 5)
+                    del SA
+                rows.append(row)
+                print(json.dumps({"coherence_row": row}), file=sys.stderr, flush=True)
+        del U32, U64
+        torch.cuda.empty_cache()
+    return {"workload": "coherence sweep m=%d n=%d, U(alpha) = orth((1-alpha) Q_rand + alpha [I;0]) stored "
+                        "FP32, d/n in %s, s in %s, sketch seed %d" % (m, n, list(ratios), list(svals), seed),
+            "rows": rows}
+
+
 def profile_run():
     """Fixed short sequence for rocprofv3 counter passes."""
     import torch
@@ -366,6 +431,9 @@ def main():
 
     if args.profile_run:
         profile_run()
+        return
+    if args.coherence:
+        print(json.dumps({"coherence_sweep": coherence_leg()}), flush=True)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
