@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--serve", type=int, default=2000, help="measured requests of the serving leg at 200 req/s "
                    "(after a tenth as many warm-up requests); 0 = skip the leg")
     p.add_argument("--profile-run", action="store_true", help="short fixed sequence for counter passes")
+    p.add_argument("--ls-paper", action="store_true",
+                   help="run only the coherent adversarial least-squares replication and print its JSON line")
     p.add_argument("--coherence", action="store_true",
                    help="run only the coherence sweep (eta against mu(U)) and print its JSON line")
     p.add_argument("--no-paper-scheme", action="store_true",
@@ -398,6 +400,63 @@ def coherence_leg(m=1 << 21, n=1024, alphas=(0.0, 0.3, 0.5, 0.7, 0.85, 0.95, 0.9
             "rows": rows}
 
 
+def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16), tau=1e-3, noise=0.5, seed=11):
+    """The paper's coherent adversarial least-squares problem (Section 5,
+    sketch-and-solve least squares, Table 1): A = [I_n; tau G / sqrt(m-n)],
+    b = [x* + eta; (tau G / sqrt(m-n)) x*] with eta = noise * N(0,1), rows
+    of A and b permuted, A stored FP32.  For CountSketch (s = 1) and
+    SparseStack (s = 4) in every accumulation mode: the sketch-and-solve
+    residual ||A x0 - b|| / ||b|| (x0 = R^-1 Q^T S b, FP32 QR of the sketch),
+    kappa(SA), the sketch + factor time, and the residual after this
+    library's FP64 refinement."""
+    import torch
+    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    tail = torch.randn((m - n, n), dtype=torch.float64, device=dev, generator=gen) * (tau / np.sqrt(m - n))
+    xs = torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    eta = noise * torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+    perm = torch.randperm(m, device=dev, generator=gen)
+    A = torch.empty((m, n), dtype=torch.float32, device=dev)
+    b = torch.empty(m, dtype=torch.float64, device=dev)
+    top = torch.eye(n, dtype=torch.float32, device=dev)
+    A[perm[:n]] = top
+    A[perm[n:]] = tail.float()
+    b[perm[:n]] = xs + eta
+    b[perm[n:]] = tail @ xs
+    del tail, top
+    torch.cuda.empty_cache()
+    methods = (("countsketch", 1, ACC_F32), ("countsketch_mxp", 1, ACC_F16_RN), ("sparsestack", 4, ACC_F32),
+               ("sparsestack_detm", 4, ACC_F16_RN), ("sparsestack_dither", 4, ACC_F16_DITHER),
+               ("sparsestack_stoch", 4, ACC_F16_SR))
+    rows = []
+    for r in ratios:
+        d = r * n
+        for name, s, code in methods:
+            sk = Sketch(m, d, s, seed, code)
+            SA = sk.apply(A)
+            X = SA.double()
+            ev = torch.linalg.eigvalsh(X.T @ X)             # sigma^2 of SA, ascending
+            kappa = float(torch.sqrt(ev[-1] / ev[0]).item()) if ev[0] > 0 else float("inf")
+            del X, ev
+            path = "workspace" if sk.plan(0, m, n)["block_group"] == 0 else "partials"
+            del SA
+            x, info = sk.solve(A, b, raise_on_notconv=False)
+            row = {"d_over_n": r, "method": name, "sketch_path": path,
+                   "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),
+                   "rel_res_sketch_and_solve": float("%.4g" % info["rel_residual_x0"]),
+                   "kappa_SA": float("%.4g" % kappa),
+                   "rel_res_refined": float("%.4g" % info["rel_residual"]),
+                   "converged": int(info["converged"]), "inner_iters": int(info["inner_iters"])}
+            rows.append(row)
+            print(json.dumps({"ls_paper_row": row}), file=sys.stderr, flush=True)
+            del x
+        torch.cuda.empty_cache()
+    return {"workload": "coherent adversarial LS m=%d n=%d FP32, tau=%g, noise %g on the identity block, rows "
+                        "permuted; sketch seed %d" % (m, n, tau, noise, seed), "rows": rows}
+
+
 def profile_run():
     """Fixed short sequence for rocprofv3 counter passes."""
     import torch
@@ -431,6 +490,9 @@ def main():
 
     if args.profile_run:
         profile_run()
+        return
+    if args.ls_paper:
+        print(json.dumps({"ls_paper": ls_paper_leg()}), flush=True)
         return
     if args.coherence:
         print(json.dumps({"coherence_sweep": coherence_leg()}), flush=True)
