@@ -400,6 +400,67 @@ def coherence_leg(m=1 << 21, n=1024, alphas=(0.0, 0.3, 0.5, 0.7, 0.85, 0.95, 0.9
             "rows": rows}
 
 
+def ls_methods():
+    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32
+    return (("countsketch", 1, ACC_F32), ("countsketch_mxp", 1, ACC_F16_RN), ("sparsestack", 4, ACC_F32),
+            ("sparsestack_detm", 4, ACC_F16_RN), ("sparsestack_dither", 4, ACC_F16_DITHER),
+            ("sparsestack_stoch", 4, ACC_F16_SR))
+
+
+def ls_rows(A, b, ratios, seed, tag):
+    """Sketch-and-solve residual, kappa(SA), sketch + factor time and the
+    refined residual for every method of ls_methods at each d/n."""
+    import torch
+    from paper_2606_20195_amd import Sketch
+    m, n = A.shape
+    rows = []
+    for r in ratios:
+        d = r * n
+        for name, s, code in ls_methods():
+            sk = Sketch(m, d, s, seed, code)
+            SA = sk.apply(A)
+            X = SA.double()
+            ev = torch.linalg.eigvalsh(X.T @ X)             # sigma^2 of SA, ascending
+            kappa = float(torch.sqrt(ev[-1] / ev[0]).item()) if ev[0] > 0 else float("inf")
+            del X, ev, SA
+            path = "workspace" if sk.plan(0, m, n)["block_group"] == 0 else "partials"
+            x, info = sk.solve(A, b, raise_on_notconv=False)
+            row = {"problem": tag, "d_over_n": r, "method": name, "sketch_path": path,
+                   "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),
+                   "rel_res_sketch_and_solve": float("%.4g" % info["rel_residual_x0"]),
+                   "kappa_SA": float("%.4g" % kappa),
+                   "rel_res_refined": float("%.4g" % info["rel_residual"]),
+                   "converged": int(info["converged"]), "inner_iters": int(info["inner_iters"])}
+            rows.append(row)
+            print(json.dumps({"ls_paper_row": row}), file=sys.stderr, flush=True)
+            del x
+        torch.cuda.empty_cache()
+    return rows
+
+
+def dense_ls_problem(m, n, noise, offset, seed):
+    """The paper's dense synthetic problems (Section 5, dense synthetic
+    least squares): A = U diag(sigma) V^T with U, V orthogonal factors of
+    Gaussian matrices and sigma falling linearly from 100 to 1, b = A e + eta
+    (e the all-ones vector), eta = noise N(0,1) + offset.  Built in FP64 on the
+    device, A stored FP32."""
+    import torch
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    U = torch.linalg.qr(torch.randn((m, n), dtype=torch.float64, device=dev, generator=gen))[0]
+    V = torch.linalg.qr(torch.randn((n, n), dtype=torch.float64, device=dev, generator=gen))[0]
+    sig = torch.linspace(100.0, 1.0, n, dtype=torch.float64, device=dev)
+    A64 = (U * sig[None, :]) @ V.T
+    del U
+    b = A64 @ torch.ones(n, dtype=torch.float64, device=dev)
+    b += noise * torch.randn(m, dtype=torch.float64, device=dev, generator=gen) + offset
+    A = A64.float()
+    del A64
+    torch.cuda.empty_cache()
+    return A, b
+
+
 def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16), tau=1e-3, noise=0.5, seed=11):
     """The paper's coherent adversarial least-squares problem (Section 5,
     sketch-and-solve least squares, Table 1): A = [I_n; tau G / sqrt(m-n)],
@@ -410,7 +471,6 @@ def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16), tau=1e-3, noise=0.5, s
     kappa(SA), the sketch + factor time, and the residual after this
     library's FP64 refinement."""
     import torch
-    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
     dev = torch.device("cuda:0")
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -427,34 +487,17 @@ def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16), tau=1e-3, noise=0.5, s
     b[perm[n:]] = tail @ xs
     del tail, top
     torch.cuda.empty_cache()
-    methods = (("countsketch", 1, ACC_F32), ("countsketch_mxp", 1, ACC_F16_RN), ("sparsestack", 4, ACC_F32),
-               ("sparsestack_detm", 4, ACC_F16_RN), ("sparsestack_dither", 4, ACC_F16_DITHER),
-               ("sparsestack_stoch", 4, ACC_F16_SR))
-    rows = []
-    for r in ratios:
-        d = r * n
-        for name, s, code in methods:
-            sk = Sketch(m, d, s, seed, code)
-            SA = sk.apply(A)
-            X = SA.double()
-            ev = torch.linalg.eigvalsh(X.T @ X)             # sigma^2 of SA, ascending
-            kappa = float(torch.sqrt(ev[-1] / ev[0]).item()) if ev[0] > 0 else float("inf")
-            del X, ev
-            path = "workspace" if sk.plan(0, m, n)["block_group"] == 0 else "partials"
-            del SA
-            x, info = sk.solve(A, b, raise_on_notconv=False)
-            row = {"d_over_n": r, "method": name, "sketch_path": path,
-                   "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),
-                   "rel_res_sketch_and_solve": float("%.4g" % info["rel_residual_x0"]),
-                   "kappa_SA": float("%.4g" % kappa),
-                   "rel_res_refined": float("%.4g" % info["rel_residual"]),
-                   "converged": int(info["converged"]), "inner_iters": int(info["inner_iters"])}
-            rows.append(row)
-            print(json.dumps({"ls_paper_row": row}), file=sys.stderr, flush=True)
-            del x
+    rows = ls_rows(A, b, ratios, seed, "coherent")
+    del A, b
+    torch.cuda.empty_cache()
+    for tag, nz, off in (("dense_easy", 1e-3, 0.0), ("dense_hard", 1e-1, 1e-1)):
+        A, b = dense_ls_problem(m, n, nz, off, seed + 1)
+        rows += ls_rows(A, b, ratios, seed, tag)
+        del A, b
         torch.cuda.empty_cache()
-    return {"workload": "coherent adversarial LS m=%d n=%d FP32, tau=%g, noise %g on the identity block, rows "
-                        "permuted; sketch seed %d" % (m, n, tau, noise, seed), "rows": rows}
+    return {"workload": "LS m=%d n=%d FP32: coherent adversarial (tau=%g, noise %g on the identity block, rows "
+                        "permuted); dense easy (sigma 100..1, noise 1e-3 N(0,1)) and hard (noise 1e-1 N(0,1) + 0.1); "
+                        "sketch seed %d" % (m, n, tau, noise, seed), "rows": rows}
 
 
 def profile_run():
