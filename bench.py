@@ -45,9 +45,9 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--modes", default="f32,sr,dither,a32",
-                   help="extra runs to time: f32/sr/dither accumulation on the FP16 input, a32 = FP32-stored "
-                        "input with FP32 accumulation; empty = the headline run only")
+    p.add_argument("--modes", default="f32,sr,dither,bf16,a32",
+                   help="extra runs to time: f32/sr/dither/bf16 (BF16 RN output) on the FP16 input, a32 = "
+                        "FP32-stored input with FP32 accumulation; empty = the headline run only")
     p.add_argument("--ls-solves", type=int, default=30, help="timed solves per path in the least-squares leg "
                    "(0 = skip the leg)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched leg")
@@ -529,7 +529,7 @@ def main():
 
     import torch
     import workloads
-    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
+    from paper_2606_20195_amd import ACC_BF16_RN, ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
 
     if args.profile_run:
         profile_run()
@@ -571,7 +571,7 @@ def main():
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
 
     modes = {}
-    mode_codes = {"f32": ACC_F32, "sr": ACC_F16_SR, "dither": ACC_F16_DITHER}
+    mode_codes = {"f32": ACC_F32, "sr": ACC_F16_SR, "dither": ACC_F16_DITHER, "bf16": ACC_BF16_RN}
     extra = [m for m in args.modes.split(",") if m]
     for name in [m for m in extra if m in mode_codes]:
         code = mode_codes[name]

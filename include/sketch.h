@@ -55,6 +55,9 @@ extern "C" {
 #define SK_ACC_F16_RN     1  /* SA is FP16, round-to-nearest-even            */
 #define SK_ACC_F16_SR     2  /* SA is FP16, exact stochastic rounding        */
 #define SK_ACC_F16_DITHER 3  /* SA is FP16, dithered rounding                */
+#define SK_ACC_BF16_RN    4  /* SA is BF16, round-to-nearest-even            */
+#define SK_ACC_BF16_SR    5  /* SA is BF16, exact stochastic rounding        */
+#define SK_ACC_BF16_DITHER 6 /* SA is BF16, dithered rounding (2^-7 scale)   */
 
 /* ---- sketch_apply flags ------------------------------------------------ */
 #define SK_ACCUMULATE 1u     /* SA += S*A instead of SA = S*A                 */
@@ -128,6 +131,16 @@ int sketch_destroy(sk_handle h);
  * FP32 mode: SA = fl32(fl32(1/sqrt(s)) * sum) with the sum accumulated in
  * FP32 in an unspecified order (exact for integer-valued A whose partial sums
  * stay below 2^24).  FP16 modes: see sk_schedule.
+ * BF16 modes: BF16 keeps 8 significant bits, so summing unit partials in
+ * BF16 would cost about 2^-9 per addition; instead the whole call is summed
+ * in FP32 (the FP32 mode's partials, added into a d x n FP32 workspace the
+ * handle allocates on first need) and each entry is rounded once to BF16
+ * with the handle's rule at site q = row_offset*d*n + b*n + c (SR: exact
+ * stochastic rounding between the BF16 neighbours; dither: round-to-nearest
+ * of fma(u*2^-24 - 1/2, x*2^-7, x)), then stored, or added to SA with one
+ * BF16 round-to-nearest addition under SK_ACCUMULATE.  BF16 SA needs 2-byte
+ * alignment only.  BF16 handles are not accepted by batches, sketch_solve or
+ * the request server (SK_EUNSUPPORTED).
  * When d/s bucket rows of 32 FP32 values do not fit in LDS (d/s above about
  * 1200), the whole call is one unit: its unscaled contributions are summed
  * with FP32 atomics in a d x n FP32 workspace that the handle allocates on
@@ -167,11 +180,12 @@ int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t *buckets,
                 int8_t *signs, void *stream);
 
 /*
- * sketch_quantize -- the FP16 rounding rules of Section 4.2 applied to
+ * sketch_quantize -- the 16-bit rounding rules of Section 4.2 applied to
  * `count` FP32 values: out[k] = Q_mode(x[k]) with rounding noise of site
- * site0 + k under (seed, epoch).  mode: SK_ACC_F16_RN / _SR / _DITHER.  x and
- * out are device arrays (out receives FP16 bit patterns).  A testing export
- * of exactly the quantiser the FP16 modes of sketch_apply use.
+ * site0 + k under (seed, epoch).  mode: SK_ACC_F16_RN / _SR / _DITHER (FP16
+ * bit patterns) or SK_ACC_BF16_RN / _SR / _DITHER (BF16 bit patterns).  x
+ * and out are device arrays.  A testing export of exactly the quantisers
+ * the 16-bit modes of sketch_apply use.
  * Errors: SK_EINVAL, SK_EHIP.
  */
 int sketch_quantize(int32_t mode, const float *x, uint16_t *out, int64_t count, uint64_t seed,

@@ -29,6 +29,9 @@ Rounding-noise stream (the paper calls an unspecified random_uint(), Section
 """
 from __future__ import annotations
 
+import math
+from fractions import Fraction
+
 import numpy as np
 
 from .philox import philox, split64
@@ -182,3 +185,56 @@ def apply_per_contribution_model(A, d, s, seed, mode, epoch=0, row_offset=0, SA0
             else:
                 acc[b[i]] = (acc[b[i]] + qv[i]).astype(np.float32)
     return acc
+
+
+ACC_BF16_RN, ACC_BF16_SR, ACC_BF16_DITHER = 4, 5, 6
+
+
+def apply_bf16_model(A, d, s, seed, mode, epoch, row_offset=0, SA0=None):
+    """BF16 output: the whole call is summed in FP32 and each entry rounded
+    once (BF16 keeps 8 significant bits, so adding unit partials in BF16 would
+    lose about 2**-9 per addition; the library keeps FP32 global partials).
+
+    The sum is taken as fl32 of the exact FP64 sum (exact for integer A whose
+    sums stay below 2**24), scaled by c_s32 in FP32, rounded with the BF16
+    rule (noise site q = row_offset*d*n + b*n + c), and stored, or added to
+    SA0 with one BF16 round-to-nearest addition.  Returns float64 BF16 values.
+    """
+    from .quant import quantize_bf16
+    check_shape(d, s)
+    A = np.asarray(A)
+    n = A.shape[1]
+    P = apply_f64(A, d, s, seed, row_offset, scale=1.0).astype(np.float32)
+    v = (c_s32(s) * P).astype(np.float32)
+    u = None
+    if mode in (ACC_BF16_SR, ACC_BF16_DITHER):
+        site = (np.uint64(row_offset) * np.uint64(d * n) + np.arange(d, dtype=np.uint64)[:, None] * np.uint64(n)
+                + np.arange(n, dtype=np.uint64)[None, :])
+        u = round_u24(seed, epoch, site)
+    q = quantize_bf16(mode, v, u)
+    if SA0 is None:
+        return q
+    # two BF16 numbers sum exactly in FP64 unless their exponents differ by
+    # more than 44, and then the smaller cannot affect the BF16 rounding
+    return rnb16_from_f64(np.asarray(SA0, dtype=np.float64) + q)
+
+
+def rnb16_from_f64(s):
+    """Round-to-nearest-even to BF16 of FP64 values, by exact rationals."""
+    s = np.asarray(s, dtype=np.float64)
+    out = np.empty_like(s)
+    for idx in np.ndindex(s.shape):
+        v = float(s[idx])
+        if v == 0 or math.isinf(v) or math.isnan(v):
+            out[idx] = v
+            continue
+        _, e = math.frexp(abs(v))                     # 2**(e-1) <= |v| < 2**e
+        te = max(e - 1, -126) - 7                     # BF16 spacing exponent at |v|
+        fr = Fraction(abs(v)) / Fraction(2) ** te
+        k = fr.numerator // fr.denominator
+        rem = fr - k
+        if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and k % 2 == 1):
+            k += 1
+        mag = math.ldexp(float(k), te)
+        out[idx] = -mag if v < 0 else mag
+    return out

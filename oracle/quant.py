@@ -244,3 +244,93 @@ def quantize(mode, x, u=None):
     if mode == 3:
         return dither16(x, u)
     raise ValueError("mode must be 1 (RN), 2 (SR) or 3 (dither)")
+
+
+# ---- BF16 (the high 16 bits of an FP32: 8 significant bits, FP32's exponent
+# range).  The same three rules, with the BF16 neighbours; the dither's noise
+# scale is read as the BF16 machine epsilon 2**-7 (about one BF16 ULP), by the
+# same reading as F = 2**-10 for FP16.  Values are returned as float64 arrays
+# (every BF16 number is exact in FP64); bf16_bits gives the bit patterns.
+
+BF16_MAX = (2.0 - 2.0 ** -7) * 2.0 ** 127
+DITHER_F_BF16 = 2.0 ** -7
+
+
+def _to_bf16(x, mode_pos, mode_neg):
+    """Round FP32 x to BF16 (magnitude rounding per sign), as float64."""
+    x = np.asarray(x, dtype=np.float32)
+    bits = x.view(np.uint32).astype(np.int64)
+    neg = (bits >> 31) & 1
+    ex = (bits >> 23) & 0xFF
+    f = bits & 0x7FFFFF
+    M = np.where(ex > 0, f | (1 << 23), f)
+    E = np.maximum(ex, 1) - 150                       # |x| = M * 2**E
+    te = np.maximum(ex - 127, -126) - 7               # BF16 spacing exponent at |x|
+    how = np.where(neg == 1, mode_neg, mode_pos)
+    k = _round_mag(M, te - E, how)
+    mag = k.astype(np.float64) * np.exp2(te.astype(np.float64))
+    over = mag > BF16_MAX
+    mag = np.where(over, np.where(how == TRUNC, BF16_MAX, np.inf), mag)
+    mag = np.where(ex == 0xFF, np.where(f == 0, np.inf, np.nan), mag)
+    return np.where(neg == 1, -mag, mag)
+
+
+def rnb16(x):
+    """Round-to-nearest-even to BF16."""
+    return _to_bf16(x, NEAREST, NEAREST)
+
+
+def rdb16(x):
+    """Largest BF16 <= x."""
+    return _to_bf16(x, TRUNC, CEIL)
+
+
+def rub16(x):
+    """Smallest BF16 >= x."""
+    return _to_bf16(x, CEIL, TRUNC)
+
+
+def srb16(x, u):
+    """Exact stochastic rounding of FP32 x to BF16 with 24-bit integers u."""
+    x, u = np.broadcast_arrays(np.asarray(x, dtype=np.float32),
+                               np.asarray(u, dtype=np.uint64) & np.uint64(U24))
+    lo, hi = rdb16(x), rub16(x)
+    xd = x.astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        take_hi = (u.astype(np.float64) * 2.0 ** -24) * (hi - lo) < (xd - lo)    # all exact in FP64
+    out = np.where(take_hi, hi, lo)
+    return np.where((np.abs(xd) > BF16_MAX) | np.isnan(xd), rnb16(x), out)
+
+
+def ditherb16(x, u):
+    """Dithered rounding to BF16: RN_bf16(fma32(u*2**-24 - 1/2, fl32(x*2**-7), x))."""
+    x = np.asarray(x, dtype=np.float32)
+    u = np.asarray(u, dtype=np.uint64) & np.uint64(U24)
+    x, u = np.broadcast_arrays(x, u)
+    y = np.empty(x.shape, dtype=np.float32)
+    xf_all = x * np.float32(DITHER_F_BF16)
+    for idx in np.ndindex(x.shape):
+        xv = float(x[idx])
+        if math.isnan(xv) or math.isinf(xv):
+            y[idx] = xv
+            continue
+        t = int(u[idx]) * 2.0 ** -24 - 0.5
+        y[idx] = np.float32(fma32(t, float(xf_all[idx]), xv))
+    return rnb16(y)
+
+
+def quantize_bf16(mode, x, u=None):
+    """Dispatch for the BF16 rounding codes: 4 = RN, 5 = SR, 6 = dither."""
+    if mode == 4:
+        return rnb16(x)
+    if mode == 5:
+        return srb16(x, u)
+    if mode == 6:
+        return ditherb16(x, u)
+    raise ValueError("mode %r is not a BF16 rounding code" % (mode,))
+
+
+def bf16_bits(v):
+    """Bit patterns (uint16) of BF16 values held in float64 (NaN -> quiet NaN)."""
+    b = (np.asarray(v, dtype=np.float64).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return np.where(np.isnan(v), (b | np.uint16(0x40)).astype(np.uint16), b)

@@ -12,13 +12,15 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, ACCUMULATE, BF16, ENOTCONV, F16, F32,
+from ._lib import (ACC_BF16_DITHER, ACC_BF16_RN, ACC_BF16_SR, ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32,
+                   ACCUMULATE, BF16, ENOTCONV, F16, F32,
                    Problem, Request, Result, Schedule, ServerInfo, SketchError, SolveInfo, SolveOpts, check, load)
 
 __all__ = ["Sketch", "SketchError", "Schedule", "Batch", "Server", "simulate_admission", "tune_batch", "load_tuning", "clear_tuning", "quantize",
            "qr_f32", "trinv_f32", "version", "ACC_F32",
            "ACC_F16_RN",
-           "ACC_F16_SR", "ACC_F16_DITHER", "F32", "F16", "BF16", "ACCUMULATE"]
+           "ACC_F16_SR", "ACC_F16_DITHER", "ACC_BF16_RN", "ACC_BF16_SR", "ACC_BF16_DITHER", "F32", "F16", "BF16",
+           "ACCUMULATE"]
 
 
 def _torch():
@@ -81,7 +83,9 @@ class Sketch:
     @property
     def out_dtype(self):
         torch = _torch()
-        return torch.float32 if self.rounding == ACC_F32 else torch.float16
+        if self.rounding == ACC_F32:
+            return torch.float32
+        return torch.bfloat16 if self.rounding >= ACC_BF16_RN else torch.float16
 
     def empty_output(self, n, device=None):
         torch = _torch()
@@ -356,7 +360,8 @@ def trinv_f32(R, stream=None):
 
 
 def quantize(mode, x, seed=0, epoch=0, site0=0, stream=None):
-    """FP16 bit patterns (int16 tensor) of x (FP32 device tensor) under rule `mode`."""
+    """16-bit patterns (int16 tensor) of x (FP32 device tensor) under rule
+    `mode`: FP16 for ACC_F16_*, BF16 for ACC_BF16_*."""
     torch = _torch()
     if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
         raise ValueError("x must be a contiguous FP32 device tensor")

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsketch.so")
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOTCONV, EADMIT, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F16, BF16 = 0, 1, 2
 ACC_F32, ACC_F16_RN, ACC_F16_SR, ACC_F16_DITHER = 0, 1, 2, 3
+ACC_BF16_RN, ACC_BF16_SR, ACC_BF16_DITHER = 4, 5, 6
 ACCUMULATE = 1
 
 EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedule", "sketch_plan",

@@ -85,7 +85,8 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         *out = pl;
         return SK_OK;
     }
-    const bool dual = h->rounding == SK_ACC_F32;   // FP32 mode keeps two fields per element
+    // FP32 partials (two fields per element) for FP32 and BF16 output
+    const bool dual = h->rounding == SK_ACC_F32 || h->rounding >= SK_ACC_BF16_RN;
     Plan pl;
     // blocks per workgroup
     if (f && f->block_group) {
@@ -180,7 +181,7 @@ int sketch_create(int64_t m, int64_t d, int32_t s, uint64_t seed, int32_t roundi
     if (s < 1 || s > 16) return set_error(SK_EINVAL, "s = %d must be in 1..16", s);
     if (d < 1 || d % s) return set_error(SK_EINVAL, "d = %lld must be >= 1 and a multiple of s = %d", (long long)d, s);
     if (d / s > (1LL << 24)) return set_error(SK_EUNSUPPORTED, "d/s = %lld too large", (long long)(d / s));
-    if (rounding < SK_ACC_F32 || rounding > SK_ACC_F16_DITHER)
+    if (rounding < SK_ACC_F32 || rounding > SK_ACC_BF16_DITHER)
         return set_error(SK_EINVAL, "unknown rounding code %d", rounding);
     sk_sketch* h = new (std::nothrow) sk_sketch;
     if (!h) return set_error(SK_ENOMEM, "out of host memory");
@@ -252,10 +253,12 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     if (ldsa < n) return set_error(SK_EINVAL, "ldsa = %lld < n = %lld", (long long)ldsa, (long long)n);
     if (rows > 0 && !A) return set_error(SK_EINVAL, "A is NULL");
     if (flags & ~SK_ACCUMULATE) return set_error(SK_EINVAL, "unknown flags 0x%x", flags);
-    const bool f16 = h->rounding != SK_ACC_F32;
+    const bool bf16 = h->rounding >= SK_ACC_BF16_RN;
+    const bool f16 = h->rounding != SK_ACC_F32 && !bf16;
     if (f16 && (((uintptr_t)SA & 3u) || (ldsa & 1)))
         return set_error(SK_EUNSUPPORTED, "FP16 SA needs a 4-byte aligned base and an even ldsa");
-    if (!f16 && ((uintptr_t)SA & 3u)) return set_error(SK_EINVAL, "FP32 SA is not 4-byte aligned");
+    if (bf16 && ((uintptr_t)SA & 1u)) return set_error(SK_EINVAL, "BF16 SA is not 2-byte aligned");
+    if (!f16 && !bf16 && ((uintptr_t)SA & 3u)) return set_error(SK_EINVAL, "FP32 SA is not 4-byte aligned");
     if (rows > 0 && ((uintptr_t)A % (uintptr_t)esz)) return set_error(SK_EINVAL, "A is not element aligned");
     const bool accumulate = (flags & SK_ACCUMULATE) != 0;
 
@@ -302,6 +305,25 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
         h->ws_floats = need;
         return SK_OK;
     };
+    if (bf16) {
+        // FP32 sum of the whole call in the workspace, one BF16 rounding per entry
+        if (rows == 0) {
+            if (!accumulate && (e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");
+            return SK_OK;
+        }
+        if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
+        if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+        a.SA = h->ws;
+        a.ldsa = n;
+        a.mode = 0;
+        a.scale = 1.0f;
+        e = pl.global ? launch_contrib(a_dtype, a, st) : launch_apply(a_dtype, pl, a, st);
+        if (e != hipSuccess) return hip_fail(e, "apply kernel");
+        e = launch_finish_bf16(h->ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
+                               (uint64_t)row_offset * (uint64_t)h->d * (uint64_t)n, round_epoch, a.k0, a.k1,
+                               accumulate, st);
+        return e == hipSuccess ? SK_OK : hip_fail(e, "finish kernel");
+    }
     if (pl.global) {
         // d/s bucket rows beyond LDS: the whole call is one unit, summed
         // unscaled in an FP32 workspace with FP32 atomics, then finished once.
@@ -400,7 +422,8 @@ int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t* buckets,
 int sketch_quantize(int32_t mode, const float* x, uint16_t* out, int64_t count, uint64_t seed, uint32_t epoch,
                     uint64_t site0, void* stream)
 {
-    if (mode < SK_ACC_F16_RN || mode > SK_ACC_F16_DITHER) return set_error(SK_EINVAL, "mode %d is not FP16", mode);
+    if (mode < SK_ACC_F16_RN || mode > SK_ACC_BF16_DITHER)
+        return set_error(SK_EINVAL, "mode %d is not a 16-bit rounding mode", mode);
     if (count < 0) return set_error(SK_EINVAL, "count < 0");
     if (count > 0 && (!x || !out)) return set_error(SK_EINVAL, "NULL array");
     if (count == 0) return SK_OK;

@@ -746,8 +746,9 @@ __global__ void quantize_kernel(int mode, const float* x, uint16_t* out, int64_t
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t u = (mode >= 2) ? round_bits(site0 + (uint64_t)t, epoch, k0, k1) : 0u;
-        out[t] = quantize(mode, x[t], u);
+        const bool noisy = mode == 2 || mode == 3 || mode == 5 || mode == 6;
+        const uint32_t u = noisy ? round_bits(site0 + (uint64_t)t, epoch, k0, k1) : 0u;
+        out[t] = mode >= 4 ? quantize_bf16(mode, x[t], u) : quantize(mode, x[t], u);
     }
 }
 

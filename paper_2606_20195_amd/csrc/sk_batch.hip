@@ -242,8 +242,10 @@ int check_problem(const sk_problem& p, int idx)
     if (p.s < 1 || p.s > 16) return set_error(SK_EINVAL, "problem %d: s = %d must be in 1..16", idx, p.s);
     if (p.d < 1 || p.d % p.s) return set_error(SK_EINVAL, "problem %d: d must be a positive multiple of s", idx);
     if (p.d / p.s > (1LL << 24)) return set_error(SK_EUNSUPPORTED, "problem %d: d/s too large", idx);
-    if (p.rounding < SK_ACC_F32 || p.rounding > SK_ACC_F16_DITHER)
+    if (p.rounding < SK_ACC_F32 || p.rounding > SK_ACC_BF16_DITHER)
         return set_error(SK_EINVAL, "problem %d: unknown rounding %d", idx, p.rounding);
+    if (p.rounding >= SK_ACC_BF16_RN)
+        return set_error(SK_EUNSUPPORTED, "problem %d: BF16 output is not supported in batches", idx);
     const int esz = esize(p.a_dtype);
     if (!esz) return set_error(SK_EINVAL, "problem %d: unknown element type %d", idx, p.a_dtype);
     if (!p.A || !p.SA) return set_error(SK_EINVAL, "problem %d: NULL A or SA", idx);

@@ -102,6 +102,32 @@ __global__ __launch_bounds__(kContribThreads) void finish16_kernel(const float* 
     }
 }
 
+// BF16 finish: SA[b][c] = rounding of fl32(scale * ws[b][c]) to BF16 (mode 4
+// RN, 5 SR, 6 dither; site q = site0 + b*n + c), or with `accumulate` the
+// round-to-nearest BF16 sum of SA[b][c] and that rounding.  One thread per
+// entry, plain stores.  Two BF16 values add exactly in FP32 whenever their
+// exponents differ by at most 16; otherwise the smaller is below a quarter
+// of the larger's spacing and FP32 rounding cannot reach a BF16 midpoint,
+// so the FP32 sum rounded to BF16 is the correctly rounded BF16 sum.
+__global__ __launch_bounds__(kContribThreads) void finish_bf16_kernel(const float* ws, int64_t d, int32_t n,
+                                                                      uint16_t* SA, int64_t ldsa, int32_t mode,
+                                                                      float scale, uint64_t site0, uint32_t epoch,
+                                                                      uint32_t k0, uint32_t k1, int32_t accumulate)
+{
+    const int64_t total = d * n;
+    for (int64_t e = (int64_t)blockIdx.x * kContribThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kContribThreads) {
+        const int64_t b = e / n;
+        const int c = (int)(e - b * n);
+        const uint64_t q = site0 + (uint64_t)b * (uint64_t)n + (uint64_t)c;
+        const uint32_t u = mode != 4 ? round_bits(q, epoch, k0, k1) : 0u;
+        uint16_t h = quantize_bf16(mode, ws[e] * scale, u);
+        uint16_t* dst = SA + b * ldsa + c;
+        if (accumulate) h = b16_rn(b16_val(*dst) + b16_val(h));
+        *dst = h;
+    }
+}
+
 template <typename AT>
 hipError_t contrib_typed(const ApplyArgs& a, hipStream_t st)
 {
@@ -126,6 +152,18 @@ hipError_t launch_finish16(const float* ws, int64_t d, int32_t n, uint16_t* SA, 
     const int64_t blocks = (total + kContribThreads - 1) / kContribThreads;
     hipLaunchKernelGGL(finish16_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(kContribThreads), 0,
                        st, ws, d, n, SA, ldsa, mode, scale, site0, epoch, k0, k1);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_bf16(const float* ws, int64_t d, int32_t n, uint16_t* SA, int64_t ldsa, int32_t mode,
+                              float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, bool accumulate,
+                              hipStream_t st)
+{
+    const int64_t total = d * n;
+    if (total == 0) return hipSuccess;
+    const int64_t blocks = (total + kContribThreads - 1) / kContribThreads;
+    hipLaunchKernelGGL(finish_bf16_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(kContribThreads), 0,
+                       st, ws, d, n, SA, ldsa, mode, scale, site0, epoch, k0, k1, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -136,4 +136,53 @@ __device__ __forceinline__ uint16_t quantize(int mode, float x, uint32_t u)
     return q_rn(x);
 }
 
+// ---- FP32 -> BF16 rounding rules (BF16 = the high 16 bits of an FP32) -------
+
+__device__ __forceinline__ float b16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Round-to-nearest-even; NaN stays NaN (quiet, sign kept), overflow gives inf.
+__device__ __forceinline__ uint16_t b16_rn(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+// Exact stochastic rounding (the rule of the FP16 one with BF16 neighbours):
+// x lies between trunc (toward zero) and the next BF16 away from zero at
+// fraction f/2^16 of the spacing, f = the low 16 bits of x, so with 24 random
+// bits the test u*2^-24 * (ru - rd) < x - rd is the integer test u < dist*2^8,
+// dist = f for x > 0 and 2^16 - f for x < 0.  Beyond the largest finite BF16
+// (and for inf / NaN) the result is the round-to-nearest one.
+__device__ __forceinline__ uint16_t b16_sr(float x, uint32_t u)
+{
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7FFFFFFFu) > 0x7F7F0000u) return b16_rn(x);
+    const uint32_t f = b & 0xFFFFu;
+    const uint16_t trunc = (uint16_t)(b >> 16);
+    if (f == 0) return trunc;
+    const uint16_t away = (uint16_t)(trunc + 1u);     // one spacing further from zero
+    const bool neg = (b >> 31) != 0;
+    const uint32_t dist = neg ? 0x10000u - f : f;
+    const uint16_t ru = neg ? trunc : away, rd = neg ? away : trunc;
+    return ((u & 0xFFFFFFu) < (dist << 8)) ? ru : rd;
+}
+
+// Dithered rounding with the BF16 epsilon: RN_bf16(fma(u*2^-24 - 1/2, x*2^-7, x)).
+__device__ __forceinline__ uint16_t b16_dither(float x, uint32_t u)
+{
+    if (!isfinite(x)) return b16_rn(x);
+    const float t = (float)(u & 0xFFFFFFu) * 0x1p-24f - 0.5f;
+    const float y = __builtin_fmaf(t, x * 0x1p-7f, x);
+    return b16_rn(y);
+}
+
+// mode: 4 RN, 5 SR, 6 dither (BF16 output).
+__device__ __forceinline__ uint16_t quantize_bf16(int mode, float x, uint32_t u)
+{
+    if (mode == 5) return b16_sr(x, u);
+    if (mode == 6) return b16_dither(x, u);
+    return b16_rn(x);
+}
+
 }  // namespace sk

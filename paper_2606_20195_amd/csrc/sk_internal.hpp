@@ -81,6 +81,10 @@ struct BatchDesc {
 hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
 // One global atomic per contribution (args.mode: 0 FP32 SA, 1..3 FP16 SA).
 hipError_t launch_contrib(int a_dtype, const ApplyArgs &args, hipStream_t st);
+// SA (BF16, ld ldsa) = (or += with one BF16 RN add) the BF16 rounding of fl32(scale * ws).
+hipError_t launch_finish_bf16(const float *ws, int64_t d, int32_t n, uint16_t *SA, int64_t ldsa, int32_t mode,
+                              float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, bool accumulate,
+                              hipStream_t st);
 // SA (FP16, ld ldsa) += rounding of fl32(scale * ws) per entry, sites site0 + b*n + c.
 hipError_t launch_finish16(const float *ws, int64_t d, int32_t n, uint16_t *SA, int64_t ldsa, int32_t mode,
                            float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, hipStream_t st);

@@ -193,7 +193,7 @@ int check_request(const sk_request& r)
     if (r.s < 1 || r.s > 16) return set_error(SK_EINVAL, "s = %d must be in 1..16", r.s);
     if (r.d < 1 || r.d % r.s) return set_error(SK_EINVAL, "d must be a positive multiple of s");
     if (r.d / r.s > (1LL << 24)) return set_error(SK_EUNSUPPORTED, "d/s too large");
-    if (r.rounding < SK_ACC_F32 || r.rounding > SK_ACC_F16_DITHER)
+    if (r.rounding < SK_ACC_F32 || r.rounding > SK_ACC_BF16_DITHER)
         return set_error(SK_EINVAL, "unknown rounding %d", r.rounding);
     if (r.gen < 0 || r.gen > 2) return set_error(SK_EINVAL, "gen must be 0, 1 or 2");
     if (!esize(r.a_dtype)) return set_error(SK_EINVAL, "unknown element type %d", r.a_dtype);

@@ -1298,6 +1298,7 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     j->b = b;
     j->x = x;
     j->o = o;
+    if (S.rounding >= SK_ACC_BF16_RN) return set_error(SK_EUNSUPPORTED, "sketch_solve takes FP32 or FP16 sketches");
     j->f16 = S.rounding != SK_ACC_F32;
     j->ldm = n + 1;
     j->ld16 = (n + 1) / 2 * 2;

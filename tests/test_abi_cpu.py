@@ -53,7 +53,7 @@ def test_create_validation(lib):
     assert _create(lib, s=17)[0] == _lib.EINVAL
     assert _create(lib, d=30, s=4)[0] == _lib.EINVAL          # d % s != 0
     assert b"multiple" in lib.sketch_last_error()
-    assert _create(lib, rounding=4)[0] == _lib.EINVAL
+    assert _create(lib, rounding=7)[0] == _lib.EINVAL          # 4..6 are the BF16 rules
     assert lib.sketch_create(10, 8, 1, 0, 0, None) == _lib.EINVAL
     rc, h = _create(lib)
     assert rc == 0 and h.value

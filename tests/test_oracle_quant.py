@@ -125,3 +125,66 @@ def test_dither_mean_matches_continuous_noise_closed_form(x):
     assert abs(float(quant.dither16_mean(x)) - mean) < 2 * 2.0 ** -13 * ulp
     if abs(float(x) - 1 / np.sqrt(8)) < 1e-7:
         assert (float(quant.dither16_mean(x)) - float(x)) / ulp == pytest.approx(0.0641, abs=2e-3)
+
+
+# ---- BF16 rules: pinned by torch's bfloat16 cast (round-to-nearest-even),
+# bracketing of the directed roundings, an exhaustive count of the SR
+# decision and the dither's bounds and mean.
+
+def _bf16_samples():
+    g = np.random.default_rng(17)
+    x = g.standard_normal(20000).astype(np.float32) * np.float32(10.0) ** g.integers(-40, 38, 20000).astype(np.float32)
+    extra = np.array([0.0, -0.0, 1.00390625, 1.01171875, -1.01171875, 3.3895314e38, 3.4e38, -3.4e38, np.inf,
+                      -np.inf, 1e-40, -1e-41, 2.0 ** -133, 3 * 2.0 ** -134], dtype=np.float32)
+    return np.concatenate([x[np.isfinite(x)], extra])
+
+
+def test_bf16_rn_matches_torch_cast():
+    torch = pytest.importorskip("torch")
+    x = _bf16_samples()
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(quant.bf16_bits(quant.rnb16(x)), ref)
+
+
+def test_bf16_directed_roundings_bracket():
+    torch = pytest.importorskip("torch")
+    x = _bf16_samples()
+    x = x[np.isfinite(x) & (np.abs(x) <= quant.BF16_MAX)]
+    lo, hi = quant.rdb16(x), quant.rub16(x)
+    xd = x.astype(np.float64)
+    assert np.all(lo <= xd) and np.all(hi >= xd)
+    exact = lo == hi
+    assert np.all(lo[exact] == xd[exact])
+    # adjacent: nothing representable strictly between them
+    for v_lo, v_hi in zip(lo[~exact][:500], hi[~exact][:500]):
+        b = torch.tensor([v_lo], dtype=torch.float64).to(torch.bfloat16).view(torch.int16).item() & 0xFFFF
+        nxt = torch.tensor([b + (1 if v_lo >= 0 else -1)], dtype=torch.int32).to(torch.int16).view(torch.bfloat16)
+        assert float(nxt.double().item()) == v_hi or (v_lo == 0 and v_hi > 0)
+
+
+@pytest.mark.parametrize("x", [1.0 + 2.0 ** -9, -(3.0 + 2.0 ** -8 + 2.0 ** -12), 7.3e-39, 1.234567e20])
+def test_bf16_sr_exhaustive_probability(x):
+    x32 = np.float32(x)
+    u = np.arange(1 << 24, dtype=np.uint64)
+    out = quant.srb16(np.full(u.shape, x32), u)
+    lo, hi = float(quant.rdb16(x32)), float(quant.rub16(x32))
+    ups = int(np.count_nonzero(out == hi))
+    assert np.all((out == hi) | (out == lo))
+    p = (Fraction(float(x32)) - Fraction(lo)) / (Fraction(hi) - Fraction(lo))
+    assert Fraction(ups, 1 << 24) == p                          # exact: p has at most 16 fraction bits
+
+
+def test_bf16_sr_beyond_range_is_rn():
+    x = np.array([3.39e38, -3.4e38, np.inf, -np.inf], dtype=np.float32)
+    assert np.array_equal(quant.bf16_bits(quant.srb16(x, 123)), quant.bf16_bits(quant.rnb16(x)))
+
+
+def test_bf16_dither_bounds_and_mean():
+    g = np.random.default_rng(3)
+    x = np.float32(1.0 + 3 * 2.0 ** -10)                         # 3/8 of a BF16 spacing above 1
+    u = g.integers(0, 1 << 24, 4000).astype(np.uint64)
+    out = quant.ditherb16(np.full(u.shape, x), u)
+    assert set(np.unique(out)) <= {1.0, 1.0 + 2.0 ** -7}
+    # noise = t * x * 2**-7, t uniform on [-1/2, 1/2): P(up) = P(t x 2**-7 > 1/8 spacing) = 1/2 - 1/8 / x
+    p_up = 0.5 - 0.125 / float(x)
+    assert abs(np.mean(out == 1.0 + 2.0 ** -7) - p_up) < 4 * np.sqrt(p_up * (1 - p_up) / len(u))
