@@ -261,3 +261,18 @@ def test_workspace_path_gaussian_tolerances_and_accumulate():
     sk.apply(Ad[25000:], SA=SA, row_offset=25000, accumulate=True)
     torch.cuda.synchronize()
     assert rel_fro(SA.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("rounding", [ACC_F32, ACC_F16_RN])
+def test_workspace_path_empty_row_range(rounding):
+    sk = Sketch(1000, 4096, 1, 2, rounding)
+    assert sk.plan(1, 1000, 8)["block_group"] == 0
+    dt = torch.float32 if rounding == ACC_F32 else torch.float16
+    SA = torch.full((4096, 8), 3.0, dtype=dt, device="cuda")
+    A = torch.zeros((0, 8), dtype=dt, device="cuda")
+    sk.apply(A, SA=SA, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 3.0)
+    sk.apply(A, SA=SA)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 0)

@@ -81,3 +81,15 @@ def test_bf16_handles_are_refused_by_batches_and_solve():
     with pytest.raises(SketchError) as ei:
         Batch([dict(A=A, SA=SA, d=64, s=4, seed=1, rounding=ACC_BF16_RN)])
     assert ei.value.code == -2
+
+
+def test_empty_row_range_clears_or_keeps():
+    sk = Sketch(1000, 64, 4, 2, ACC_BF16_SR)
+    A = torch.zeros((0, 8), dtype=torch.float16, device="cuda")
+    SA = torch.full((64, 8), 3.0, dtype=torch.bfloat16, device="cuda")
+    sk.apply(A, SA=SA, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 3.0)
+    sk.apply(A, SA=SA)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 0)

@@ -106,3 +106,18 @@ def test_fp32_per_contribution_non_power_of_two_scale():
     got = run(A, 20000, 256, 8, 6, ACC_F32).astype(np.float64)
     ref = apply_f64(A, 256, 8, 6)
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+@pytest.mark.parametrize("rounding", [ACC_F32, ACC_F16_RN])
+def test_empty_row_range_clears_or_keeps(rounding):
+    sk = Sketch(1000, 64, 4, 2, rounding)
+    sk.set_schedule(**PC)
+    dt = torch.float32 if rounding == ACC_F32 else torch.float16
+    A = torch.zeros((0, 8), dtype=dt, device="cuda")
+    SA = torch.full((64, 8), 3.0, dtype=dt, device="cuda")
+    sk.apply(A, SA=SA, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 3.0)
+    sk.apply(A, SA=SA)
+    torch.cuda.synchronize()
+    assert torch.all(SA == 0)
