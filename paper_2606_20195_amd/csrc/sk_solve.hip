@@ -747,7 +747,7 @@ __global__ void gram_kernel(const float* PT, int64_t ldp, int32_t n, float* M)
 // Householder factorisation of the panel M[k0:rows, k0:k0+nb] in LDS by one
 // workgroup (LAPACK slarfg convention: beta = -sign(x0) ||x||, v[0] = 1).
 __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
-                                                       int32_t nb, float* tau)
+                                                       int32_t nb, float* tau, float* Tout)
 {
     extern __shared__ float pan[];
     __shared__ float s_tau[32];
@@ -824,6 +824,52 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
         M[(int64_t)(k0 + r) * ldm + k0 + c] = pan[c * ldl + r];
     }
     if (tid < nb) tau[k0 + tid] = s_tau[tid];
+    if (!Tout) return;
+    // Triangular factor of the block reflector (forward, columnwise):
+    // H_0 H_1 ... H_{nb-1} = I - V T V^T with T[j][j] = tau_j and
+    // T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).  First the Gram
+    // entries gv[l][j] = v_l . v_j (l < j; v_j is 0 above row j and 1 on it),
+    // one wave per entry, then the recurrence with lane i holding row i of T
+    // in registers, so each step reads only its own lane and gv.
+    __shared__ float gv[32 * 33];
+    const int wave = tid >> 6, lane = tid & 63;
+    const int npairs = nb * (nb - 1) / 2;
+    for (int pi = wave; pi < npairs; pi += kT / 64) {
+        int j = 1;
+        while ((j * (j + 1)) / 2 <= pi) ++j;
+        const int l = pi - j * (j - 1) / 2;
+        const float* vl = pan + l * ldl;
+        const float* vj = pan + j * ldl;
+        float acc = 0.0f;
+        for (int r = j + 1 + lane; r < rows; r += 64) acc = __builtin_fmaf(vl[r], vj[r], acc);
+        acc = group_sum<64>(acc);
+        if (lane == 0) gv[l * 33 + j] = acc + vl[j];
+    }
+    __syncthreads();
+    if (wave == 0 && lane < nb) {
+        const int i = lane;
+        float trow[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            float val = 0.0f;
+            if (j < nb) {
+                const float tj = s_tau[j];
+                if (i == j) {
+                    val = tj;
+                } else if (i < j) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int l = 0; l < j; ++l)
+                        if (l >= i) acc = __builtin_fmaf(trow[l], gv[l * 33 + j], acc);
+                    val = -tj * acc;
+                }
+            }
+            trow[j] = val;
+        }
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+            if (j < nb) Tout[i * nb + j] = trow[j];
+    }
 }
 
 // Apply the panel's reflectors H_{k0} .. H_{k0+nb-1} to columns
@@ -832,14 +878,15 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
 // implicit unit diagonal and zeros above it written out.
 __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
                                                          int32_t nb, int32_t c0, int32_t ncols, int32_t cb,
-                                                         const float* tau, int32_t vlds)
+                                                         const float* tau, int32_t vlds, const float* Tg)
 {
     extern __shared__ float sm[];
     __shared__ float red[2][kUT / 64][kCB];
     const int rows = rows_total - k0;
     const int ldb = cb + 1;              // odd row stride: lanes of consecutive rows hit distinct banks
+    const int ldv = rows | 1;            // odd column stride of V: reflectors' rows hit distinct banks
     float* blk = sm;                     // [rows][ldb]
-    float* V = sm + (size_t)rows * ldb;  // [nb][rows]
+    float* V = sm + (size_t)rows * ldb;  // [nb][ldv]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cbase = c0 + blockIdx.x * cb;
     const int nc = min(cb, c0 + ncols - cbase);
@@ -872,13 +919,68 @@ __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, i
             for (int e = 0; e < 8; ++e) {
                 const int idx = base + e * kUT + tid;
                 const int r = idx / nb, j = idx - r * nb;
-                if (idx < rows * nb) V[(size_t)j * rows + r] = v[e];
+                if (idx < rows * nb) V[(size_t)j * ldv + r] = v[e];
             }
         }
     }
     __syncthreads();
+    if (vlds && Tg) {
+        // Block reflector: Q^T C = C - V T^T (V^T C) in three parallel phases.
+        __shared__ float Ts[32 * 32];
+        __shared__ float Wb[32][kCB + 1];
+        __shared__ float W2[32][kCB + 1];
+        for (int idx = tid; idx < nb * nb; idx += kUT) Ts[idx] = Tg[idx];
+        {   // W = V^T C: lane group of 8 per reflector i, lanes interleave the rows
+            const int i = tid >> 3, sl = tid & 7;
+            float acc[kCB];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
+            if (i < nb) {
+                for (int r = i + sl; r < rows; r += 8) {
+                    const float v = V[(size_t)i * ldv + r];
+#pragma unroll
+                    for (int c = 0; c < kCB; ++c)
+                        if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * ldb + c], acc[c]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) acc[c] = group_sum<8>(acc[c]);
+            if (sl == 0 && i < nb) {
+#pragma unroll
+                for (int c = 0; c < kCB; ++c) Wb[i][c] = acc[c];
+            }
+        }
+        __syncthreads();
+        for (int o = tid; o < nb * cb; o += kUT) {       // W2 = T^T W (T upper triangular)
+            const int i = o / cb, c = o - i * cb;
+            float acc = 0.0f;
+            for (int l = 0; l <= i; ++l) acc = __builtin_fmaf(Ts[l * nb + i], Wb[l][c], acc);
+            W2[i][c] = acc;
+        }
+        __syncthreads();
+        for (int r = tid; r < rows; r += kUT) {          // C -= V W2 (V is zero above its diagonal)
+            float acc[kCB];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
+            const int imax = min(nb - 1, r);
+            for (int i = 0; i <= imax; ++i) {
+                const float v = V[(size_t)i * ldv + r];
+#pragma unroll
+                for (int c = 0; c < kCB; ++c) acc[c] = __builtin_fmaf(v, W2[i][c], acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < kCB; ++c)
+                if (c < cb) blk[r * ldb + c] -= acc[c];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < rows * cb; idx += kUT) {
+            const int r = idx / cb, c = idx - r * cb;
+            if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[r * ldb + c];
+        }
+        return;
+    }
     auto vval = [&](int j, int r) -> float {
-        if (vlds) return V[(size_t)j * rows + r];
+        if (vlds) return V[(size_t)j * ldv + r];
         return r < j ? 0.0f : (r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j]);
     };
     for (int j = 0; j < nb; ++j) {
@@ -1071,34 +1173,38 @@ hipError_t set_lds(const void* fn, size_t bytes)
 }
 
 // In-place QR of the first k columns of M (rows x cols).
-hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float* tau, hipStream_t st)
+// Blocked Householder QR.  With T (a 32 x 32 FP32 device buffer, reused by
+// every panel in stream order) the trailing update applies each panel as one
+// block reflector; without it, reflector by reflector.
+hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, float* tau, float* T,
+                  hipStream_t st)
 {
     hipError_t e;
     for (int64_t k0 = 0; k0 < k; ) {
         const int64_t prow = rows - k0;
         const int nb = (int)std::min<int64_t>(panel_width(prow), k - k0);
         const size_t lds = (size_t)(prow | 1) * nb * 4;
+        const int64_t c0 = k0 + nb, ncols = cols - c0;
         if ((e = set_lds((const void*)qr_panel_kernel, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kT), lds, st, M, ldm, (int32_t)rows, (int32_t)k0,
-                           (int32_t)nb, tau);
+                           (int32_t)nb, tau, ncols > 0 ? T : (float*)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int64_t c0 = k0 + nb, ncols = cols - c0;
         if (ncols > 0) {
             // reflectors in LDS when they fit beside at least 4 columns, else read from L2
             int cb = 0, vlds = 0;
             for (int c : {kCB, 4}) {
-                if ((size_t)prow * (c + 1 + nb) * 4 <= 150 * 1024) {
+                if (((size_t)prow * (c + 1) + (size_t)nb * (prow | 1)) * 4 <= 150 * 1024) {
                     cb = c;
                     vlds = 1;
                     break;
                 }
             }
             if (!cb) cb = update_cols(prow);
-            const size_t ulds = (size_t)prow * (cb + 1 + (vlds ? nb : 0)) * 4;
+            const size_t ulds = ((size_t)prow * (cb + 1) + (vlds ? (size_t)nb * (prow | 1) : 0)) * 4;
             if ((e = set_lds((const void*)qr_update_kernel, ulds)) != hipSuccess) return e;
             hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((ncols + cb - 1) / cb)), dim3(kUT), ulds, st, M,
                                ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0, (int32_t)ncols,
-                               (int32_t)cb, (const float*)tau, (int32_t)vlds);
+                               (int32_t)cb, (const float*)tau, (int32_t)vlds, (const float*)T);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         k0 += nb;
@@ -1207,7 +1313,7 @@ struct SolveJob {
     Geo geo;
     RowArgs ra{};
     size_t oM = 0, o16 = 0, ob32 = 0, ou = 0, oP = 0, oPT = 0, otau = 0, ot = 0, ov = 0, ow = 0, oy = 0, opart = 0,
-           ost = 0, otk = 0, total = 0;
+           ost = 0, otk = 0, oTq = 0, total = 0;
     // device binding
     hipStream_t st = nullptr;
     char* base = nullptr;
@@ -1215,6 +1321,7 @@ struct SolveJob {
     uint16_t* SA16 = nullptr;
     float* b32 = nullptr;
     float* tau = nullptr;
+    float* Tq = nullptr;         // 32 x 32 block-reflector factor of the current QR panel
     // host resources (kept across reuses)
     SolveState* host = nullptr;  // pinned
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1315,6 +1422,7 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     j->oP = take((size_t)n * n * 4);
     j->oPT = take((size_t)n * n * 4);
     j->otau = take((size_t)n * 4 + 4);
+    j->oTq = take(32 * 32 * 4);
     j->ot = take((size_t)n * 4);
     j->ov = take((size_t)n * 8);
     j->ow = take((size_t)n * 8);
@@ -1417,6 +1525,7 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     j->SA16 = (uint16_t*)(base + j->o16);
     j->b32 = (float*)(base + j->ob32);
     j->tau = (float*)(base + j->otau);
+    j->Tq = (float*)(base + j->oTq);
     RowArgs& ra = j->ra;
     ra.u = (float*)(base + j->ou);
     ra.t = (float*)(base + j->ot);
@@ -1462,7 +1571,7 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     if ((e = job_record(j, 1)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
 
     // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
-    if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
+    if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, j->Tq, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
     if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.M, (float*)ra.PT, n, &ra.st->bad, &ra.st->rfro2, st)) != hipSuccess)
         return job_fail(j, hip_err(e, "inverse kernel"));
     hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st,
@@ -1599,7 +1708,14 @@ int sketch_qr_f32(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
     if (rows > kMaxD || cols > kMaxN + 1)
         return set_error(SK_EUNSUPPORTED, "rows <= %lld and cols <= %d", (long long)kMaxD, kMaxN + 1);
     if (k == 0) return SK_OK;
-    hipError_t e = run_qr(M, rows, cols, ldm, k, tau, (hipStream_t)stream);
+    // the block reflectors' 32 x 32 factor, allocated in stream order
+    hipStream_t st = (hipStream_t)stream;
+    float* T = nullptr;
+    hipError_t e = hipMallocAsync((void**)&T, 32 * 32 * 4, st);
+    if (e != hipSuccess) return set_error(SK_ENOMEM, "QR factor buffer: %s", hipGetErrorString(e));
+    e = run_qr(M, rows, cols, ldm, k, tau, T, st);
+    const hipError_t ef = hipFreeAsync(T, st);
+    if (e == hipSuccess) e = ef;
     return e == hipSuccess ? SK_OK : hip_err(e, "QR kernels");
 }
 
