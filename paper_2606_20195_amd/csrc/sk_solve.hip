@@ -744,6 +744,35 @@ __global__ void gram_kernel(const float* PT, int64_t ldp, int32_t n, float* M)
 
 // ------------------------------------------------------------ QR (FP32)
 
+// Row i of the triangular factor T of a panel's block reflector (forward,
+// columnwise): T[i][i] = tau_i and T[i][j] = -tau_j sum_{i <= l < j} T[i][l]
+// gv[l][j] for i < j, where gv[l][j] = v_l . v_j; the lane keeps its row in
+// registers, so each step reads only its own lane and gv.  T[i][l] = 0 for
+// l < i, so the sums may run over all l < j.
+__device__ __forceinline__ void form_t(int i, int nb, const float* gv, const float* s_tau, float* Tout)
+{
+    float trow[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        float val = 0.0f;
+        if (j < nb) {
+            const float tj = s_tau[j];
+            if (i == j) {
+                val = tj;
+            } else if (i < j) {
+                float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int l = 0; l < j; ++l) acc[l & 3] = __builtin_fmaf(trow[l], gv[l * 33 + j], acc[l & 3]);
+                val = -tj * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+            }
+        }
+        trow[j] = val;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        if (j < nb) Tout[i * nb + j] = trow[j];
+}
+
 // Householder factorisation of the panel M[k0:rows, k0:k0+nb] in LDS by one
 // workgroup (LAPACK slarfg convention: beta = -sign(x0) ||x||, v[0] = 1).
 __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
@@ -846,30 +875,156 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
         if (lane == 0) gv[l * 33 + j] = acc + vl[j];
     }
     __syncthreads();
-    if (wave == 0 && lane < nb) {
-        const int i = lane;
-        float trow[32];
+    if (wave == 0 && lane < nb) form_t(lane, nb, gv, s_tau, Tout);
+}
+
+// Register-resident panel factorisation for panels of at most 4 * kPT rows:
+// thread t holds rows t, t + kPT, ... (R of them) of the nb <= 32 panel
+// columns in registers.  Step j needs one block reduction: with
+// S_c = sum_{r > j} y_rj y_rc for every column c, S_j is the norm below the
+// diagonal that fixes beta, tau and scal = 1 / (x0 - beta) (x0 = y_jj), and
+// w_c = y_jc + scal S_c is v_j . y_c for c > j (the dot product of the
+// trailing column with the reflector v_j = (1, scal * y_{r > j, j})) and
+// v_c . v_j for c < j (the Gram column of T).  The update
+// y_rc -= tau w_c v_r then touches registers only.  A wave folds its 32 sums
+// by halving (each exchange sends the half the partner keeps), leaving sum c
+// on lanes 2c and 2c + 1; 128 threads add the waves' sums and form the step's
+// coefficients.  LDS buffers alternate between steps, so two barriers a step
+// suffice.
+constexpr int kPT = 256;
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v)
+{
+    return __uint_as_float(dpp32<CTRL>(__float_as_uint(v)));
+}
+
+// One halving step of the wave fold: lanes with `hi` keep values [H, 2H), the
+// others [0, H); each adds what the partner (reached by X) sends.
+template <int H, typename X>
+__device__ __forceinline__ void fold_half(float* p, bool hi, X exch)
+{
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            float val = 0.0f;
-            if (j < nb) {
-                const float tj = s_tau[j];
-                if (i == j) {
-                    val = tj;
-                } else if (i < j) {
-                    float acc = 0.0f;
+    for (int k = 0; k < H; ++k) {
+        const float keep = hi ? p[k + H] : p[k];
+        const float send = hi ? p[k] : p[k + H];
+        p[k] = keep + exch(send);
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kPT) void qr_panel_reg_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
+                                                           int32_t nb, float* tau, float* Tout)
+{
+    __shared__ float red[2][kPT / 64][32];
+    __shared__ float piv[2][32];
+    __shared__ float coef[2][32];
+    __shared__ float stepv[2][2];
+    __shared__ float gv[32 * 33];
+    __shared__ float s_tau[32];
+    const int rows = rows_total - k0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float y0[32], y1[32], y2[32], y3[32];
+    auto each = [&](auto&& f) {
+        f(y0, 0);
+        if constexpr (R > 1) f(y1, 1);
+        if constexpr (R > 2) {
+            f(y2, 2);
+            f(y3, 3);
+        }
+    };
+    each([&](float* y, int i) {
+        const int r = tid + i * kPT;
+        const float* src = M + (int64_t)(k0 + (r < rows ? r : 0)) * ldm + k0;
+        if (nb == 32) {
 #pragma unroll
-                    for (int l = 0; l < j; ++l)
-                        if (l >= i) acc = __builtin_fmaf(trow[l], gv[l * 33 + j], acc);
-                    val = -tj * acc;
-                }
-            }
-            trow[j] = val;
+            for (int c = 0; c < 32; ++c) y[c] = src[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 32; ++c) y[c] = src[c < nb ? c : 0];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) y[c] = c < nb ? y[c] : 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 32; ++j)
-            if (j < nb) Tout[i * nb + j] = trow[j];
+        for (int c = 0; c < 32; ++c) y[c] = r < rows ? y[c] : 0.0f;
+    });
+    for (int j = 0; j < nb; ++j) {
+        const int b = j & 1;
+        float p[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) p[c] = 0.0f;
+        each([&](float* y, int i) {
+            const int r = tid + i * kPT;
+            const float a = r > j ? y[j] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) p[c] = __builtin_fmaf(a, y[c], p[c]);
+            if (r == j) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) piv[b][c] = y[c];
+            }
+        });
+        fold_half<16>(p, lane & 32, [](float v) { return __shfl_xor(v, 32); });
+        fold_half<8>(p, lane & 16,
+                     [](float v) { return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)); });
+        fold_half<4>(p, lane & 8, [](float v) { return dppf<0x140>(v); });   // row_mirror: flips lane bit 3
+        fold_half<2>(p, lane & 4, [](float v) { return dppf<0x141>(v); });   // row_half_mirror: flips bit 2
+        fold_half<1>(p, lane & 2, [](float v) { return dppf<0x4E>(v); });    // quad_perm [2,3,0,1]: bit 1
+        p[0] += dppf<0xB1>(p[0]);                                            // quad_perm [1,0,3,2]: bit 0
+        if ((lane & 1) == 0) red[b][wave][lane >> 1] = p[0];
+        __syncthreads();
+        if (tid < 32 * (kPT / 64)) {
+            const int c = tid / (kPT / 64), w = tid % (kPT / 64);
+            const float sc = group_sum<kPT / 64>(red[b][w][c]);
+            const float sig = group_sum<kPT / 64>(red[b][w][j]);
+            const float x0 = piv[b][j];
+            float t = 0.0f, beta = x0, scal = 1.0f;
+            if (sig > 0.0f) {
+                beta = -copysignf(sqrtf(__builtin_fmaf(x0, x0, sig)), x0);
+                t = (beta - x0) / beta;
+                scal = 1.0f / (x0 - beta);
+            }
+            const float wc = __builtin_fmaf(scal, sc, piv[b][c]);
+            if (w == 0) {
+                coef[b][c] = c > j ? t * wc : 0.0f;
+                if (c < j) gv[c * 33 + j] = wc;
+                if (c == 0) {
+                    stepv[b][0] = scal;
+                    stepv[b][1] = beta;
+                    s_tau[j] = t;
+                }
+            }
+        }
+        __syncthreads();
+        float cf[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) cf[c] = coef[b][c];
+        const float scal = stepv[b][0], beta = stepv[b][1];
+        each([&](float* y, int i) {
+            const int r = tid + i * kPT;
+            const float yj = y[j];
+            const float v = r > j ? scal * yj : (r == j ? 1.0f : 0.0f);
+#pragma unroll
+            for (int c = 0; c < 32; ++c) y[c] = __builtin_fmaf(-cf[c], v, y[c]);   // cf[j] = 0
+            y[j] = r > j ? v : (r == j ? beta : yj);
+        });
     }
+    each([&](float* y, int i) {
+        const int r = tid + i * kPT;
+        if (r < rows) {
+            float* dst = M + (int64_t)(k0 + r) * ldm + k0;
+            if (nb == 32) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) dst[c] = y[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 32; ++c)
+                    if (c < nb) dst[c] = y[c];
+            }
+        }
+    });
+    __syncthreads();
+    if (tid < nb) tau[k0 + tid] = s_tau[tid];
+    if (Tout && wave == 0 && lane < nb) form_t(lane, nb, gv, s_tau, Tout);
 }
 
 // Apply the panel's reflectors H_{k0} .. H_{k0+nb-1} to columns
@@ -1182,12 +1337,24 @@ hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
     hipError_t e;
     for (int64_t k0 = 0; k0 < k; ) {
         const int64_t prow = rows - k0;
-        const int nb = (int)std::min<int64_t>(panel_width(prow), k - k0);
+        const int32_t nb = (int32_t)std::min<int64_t>(panel_width(prow), k - k0);
         const size_t lds = (size_t)(prow | 1) * nb * 4;
         const int64_t c0 = k0 + nb, ncols = cols - c0;
-        if ((e = set_lds((const void*)qr_panel_kernel, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kT), lds, st, M, ldm, (int32_t)rows, (int32_t)k0,
-                           (int32_t)nb, tau, ncols > 0 ? T : (float*)nullptr);
+        float* Tp = ncols > 0 ? T : (float*)nullptr;
+        if (prow <= kPT) {
+            hipLaunchKernelGGL(qr_panel_reg_kernel<1>, dim3(1), dim3(kPT), 0, st, M, ldm, (int32_t)rows,
+                               (int32_t)k0, nb, tau, Tp);
+        } else if (prow <= 2 * kPT) {
+            hipLaunchKernelGGL(qr_panel_reg_kernel<2>, dim3(1), dim3(kPT), 0, st, M, ldm, (int32_t)rows,
+                               (int32_t)k0, nb, tau, Tp);
+        } else if (prow <= 4 * kPT) {
+            hipLaunchKernelGGL(qr_panel_reg_kernel<4>, dim3(1), dim3(kPT), 0, st, M, ldm, (int32_t)rows,
+                               (int32_t)k0, nb, tau, Tp);
+        } else {
+            if ((e = set_lds((const void*)qr_panel_kernel, lds)) != hipSuccess) return e;
+            hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(kT), lds, st, M, ldm, (int32_t)rows, (int32_t)k0,
+                               (int32_t)nb, tau, Tp);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ncols > 0) {
             // reflectors in LDS when they fit beside at least 4 columns, else read from L2

@@ -43,10 +43,14 @@ def _row_sign_normalise(R):
     return R * s[:, None]
 
 
-@pytest.mark.parametrize("rows,n", [(256, 32), (1024, 256), (300, 37), (2048, 40), (65, 64), (96, 1),
-                                    (1200, 40), (1200, 300), (500, 50), (4096, 100)])   # panels of 17-31 columns
-def test_qr_matches_fp64(rows, n):
+@pytest.mark.parametrize("rows,n,zero_col", [
+    (256, 32, None), (1024, 256, None), (300, 37, None), (2048, 40, None), (65, 64, None), (96, 1, None),
+    (1200, 40, None), (1200, 300, None), (500, 50, None), (4096, 100, None),   # panels of 17-31 columns
+    (768, 200, None), (640, 70, 5)])                                            # a zero column
+def test_qr_matches_fp64(rows, n, zero_col):
     M = workloads.gaussian(rows, n + 1, 11 + n, np.float32)
+    if zero_col is not None:
+        M[:, zero_col] = 0.0      # tau = 0 for that column: its reflector is the identity
     Md = torch.from_numpy(M).to(DEV)
     tau = qr_f32(Md, n)
     torch.cuda.synchronize()
