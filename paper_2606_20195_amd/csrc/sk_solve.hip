@@ -36,6 +36,7 @@ namespace {
 constexpr int kT = 1024;           // threads of the row passes and one-workgroup kernels
 constexpr int kWaves = kT / 64;
 constexpr int kUT = 256;           // threads of the QR trailing update
+constexpr int kTI = 256;           // threads of the triangular inverse (one column per wave)
 constexpr int kCB = 8;             // columns per trailing-update workgroup (maximum)
 constexpr int kMaxN = 1024;
 constexpr int64_t kMaxD = 16384;
@@ -124,6 +125,7 @@ __device__ __forceinline__ float sum_lanes(float v, int width)
 
 // Sum over all kT threads; every thread receives the total.  `sh` holds kWaves
 // doubles; all threads must call it.
+template <int NT = kT>
 __device__ double block_sum(double v, double* sh)
 {
     v = group_sum<64>(v);
@@ -132,7 +134,7 @@ __device__ double block_sum(double v, double* sh)
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) t += sh[i];
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
     return t;
 }
 
@@ -1181,37 +1183,40 @@ __global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, i
 }
 
 // P = R^-1 (and P^T) by back substitution: wave w of workgroup b computes
-// column j = 16 b + w; rows of R are staged through LDS 16 at a time.  The
-// last workgroup stages all of R; if rfro2 is given it stores ||R||_F^2 there.
-__global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, int32_t n, float* P, float* PT,
-                                                    int64_t ldp, int32_t* bad, double* rfro2)
+// column j = 4 b + w, lane l holding x_k for k = l + 64 q, q < Q (64 Q >= n);
+// rows of R are staged through LDS 16 at a time.  Four waves a workgroup
+// spread the columns over n / 4 compute units.  The last workgroup stages
+// all of R; if rfro2 is given it stores ||R||_F^2 there.
+template <int Q>
+__global__ __launch_bounds__(kTI) void trinv_kernel(const float* R, int64_t ldr, int32_t n, float* P, float* PT,
+                                                     int64_t ldp, int32_t* bad, double* rfro2)
 {
     extern __shared__ float rp[];        // [16][J]
-    __shared__ double red[kWaves];
+    __shared__ double red[kTI / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j = blockIdx.x * kWaves + wave;
-    const int J = min(n, (int)(blockIdx.x + 1) * kWaves);
+    const int j = blockIdx.x * (kTI / 64) + wave;
+    const int J = min(n, (int)(blockIdx.x + 1) * (kTI / 64));
     double sq = 0.0;                     // squares of the staged entries (all of R in the last workgroup)
-    float xv[16];
+    float xv[Q];                         // x_k, k = lane + 64 q: zero until solved, and for k > j
 #pragma unroll
-    for (int q = 0; q < 16; ++q) xv[q] = 0.0f;
+    for (int q = 0; q < Q; ++q) xv[q] = 0.0f;
     bool ok = true;
     for (int hi = J - 1; hi >= 0; hi -= 16) {
         const int lo = max(0, hi - 15);
         __syncthreads();
         const int cnt = (hi - lo + 1) * J;
-        for (int base = 0; base < cnt; base += 8 * kT) {
+        for (int base = 0; base < cnt; base += 8 * kTI) {
             float v[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int idx = base + e * kT + tid;
+                const int idx = base + e * kTI + tid;
                 const int rr = idx / J, k = idx - rr * J;
                 const int i = lo + rr;
                 v[e] = (idx < cnt && k >= i) ? R[(int64_t)i * ldr + k] : 0.0f;
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int idx = base + e * kT + tid;
+                const int idx = base + e * kTI + tid;
                 if (idx < cnt) rp[idx] = v[e];
                 sq = fma((double)v[e], (double)v[e], sq);
             }
@@ -1219,19 +1224,21 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
         __syncthreads();
         if (j < n) {
             for (int i = min(hi, j); i >= lo; --i) {
+                // row[k] = 0 below the diagonal and x_k = 0 for k <= i or k > j,
+                // so the sum over all staged k is the one over i < k <= j
                 const float* row = rp + (i - lo) * J;
                 float s = 0.0f;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
+                for (int q = 0; q < Q; ++q) {
                     const int k = lane + 64 * q;
-                    if (k > i && k <= j) s = __builtin_fmaf(row[k], xv[q], s);
+                    if (64 * (q + 1) <= J || k < J) s = __builtin_fmaf(row[k], xv[q], s);
                 }
                 s = group_sum<64>(s);
                 const float dgl = row[i];
                 const float xi = ((i == j ? 1.0f : 0.0f) - s) / dgl;
                 if (!(dgl != 0.0f) || !(fabsf(xi) <= 3.0e38f)) ok = false;
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
+                for (int q = 0; q < Q; ++q)
                     if (lane + 64 * q == i) xv[q] = xi;
             }
         }
@@ -1240,7 +1247,7 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
         for (int i = lane; i < n; i += 64) {
             float val = 0.0f;
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
+            for (int q = 0; q < Q; ++q)
                 if (lane + 64 * q == i) val = xv[q];
             if (i > j) val = 0.0f;
             P[(int64_t)i * ldp + j] = val;
@@ -1249,7 +1256,7 @@ __global__ __launch_bounds__(kT) void trinv_kernel(const float* R, int64_t ldr, 
         if (!ok && lane == 0) *bad = 1;
     }
     if (rfro2 && blockIdx.x == gridDim.x - 1) {
-        const double t = block_sum(sq, red);
+        const double t = block_sum<kTI>(sq, red);
         if (tid == 0) *rfro2 = t;
     }
 }
@@ -1382,11 +1389,23 @@ hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
 hipError_t run_trinv(const float* R, int64_t ldr, int64_t n, float* P, float* PT, int64_t ldp, int32_t* bad,
                      double* rfro2, hipStream_t st)
 {
-    const int64_t grid = (n + kWaves - 1) / kWaves;
-    const size_t lds = (size_t)16 * std::min<int64_t>(n, grid * kWaves) * 4;
-    hipError_t e = set_lds((const void*)trinv_kernel, lds);
+    constexpr int W = kTI / 64;
+    const int64_t grid = (n + W - 1) / W;
+    const size_t lds = (size_t)16 * n * 4;          // the last workgroup stages 16 full rows
+    const int q = n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 16;
+    const void* fn = q == 1 ? (const void*)trinv_kernel<1> : q == 2 ? (const void*)trinv_kernel<2>
+                   : q == 4 ? (const void*)trinv_kernel<4> : q == 8 ? (const void*)trinv_kernel<8>
+                   : (const void*)trinv_kernel<16>;
+    hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(trinv_kernel, dim3((unsigned)grid), dim3(kT), lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2);
+    const dim3 g((unsigned)grid), b(kTI);
+    switch (q) {
+    case 1: hipLaunchKernelGGL(trinv_kernel<1>, g, b, lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2); break;
+    case 2: hipLaunchKernelGGL(trinv_kernel<2>, g, b, lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2); break;
+    case 4: hipLaunchKernelGGL(trinv_kernel<4>, g, b, lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2); break;
+    case 8: hipLaunchKernelGGL(trinv_kernel<8>, g, b, lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2); break;
+    default: hipLaunchKernelGGL(trinv_kernel<16>, g, b, lds, st, R, ldr, (int32_t)n, P, PT, ldp, bad, rfro2); break;
+    }
     return hipGetLastError();
 }
 

@@ -68,10 +68,11 @@ def test_qr_matches_fp64(rows, n, zero_col):
     assert np.all(np.isfinite(_np(tau)))
 
 
-@pytest.mark.parametrize("n", [1, 16, 40, 256, 300])
+@pytest.mark.parametrize("n", [1, 16, 40, 100, 256, 300, 1024])   # every register width (64 q >= n)
 def test_trinv_matches_fp64(n):
     g = workloads.rng(100 + n)
-    R = np.triu(g.standard_normal((n, n)) * 0.1) + np.diag(1.0 + g.random(n))
+    sc = 0.1 if n <= 300 else 0.1 * np.sqrt(300.0 / n)            # keeps kappa(R) near 15 at n = 1024
+    R = np.triu(g.standard_normal((n, n)) * sc) + np.diag(1.0 + g.random(n))
     R = R.astype(np.float32)
     P, PT, bad = trinv_f32(torch.from_numpy(R).to(DEV))
     torch.cuda.synchronize()
