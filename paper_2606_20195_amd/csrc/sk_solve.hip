@@ -571,7 +571,14 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
         (void*)((const char*)p.A + row0 * (int64_t)rowbytes), (short)0, (int)nrec, 0x00020000);
     const bool vec = p.vec != 0, mask = p.mask != 0;
     float ss = 0.0f;
-    const int64_t step = (int64_t)kWaves * RW;
+    // With BL, a wave takes U * RW consecutive rows at a time (slot uu, row
+    // slot rs = row uu * RW + rs of the block) and moves their u in one load
+    // and one store of U * RW lanes, handing values between lanes; otherwise
+    // the slots are kWaves * RW rows apart and every row loads and stores its
+    // own u.
+    constexpr bool BL = U * RW <= 64 && U <= LR;
+    const int64_t step = BL ? RW : (int64_t)kWaves * RW;
+    const int64_t wstride = BL ? (int64_t)kWaves * U * RW : U * step;
 
     float aA[U][CP][C], aB[U][CP][C];
     float uA[U], uB[U];
@@ -583,10 +590,17 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
             const uint32_t off = valid ? (uint32_t)(row - row0) * rowbytes : nrec;
 #pragma unroll
             for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
-            uo[uu] = valid ? p.u[row] : 0.0f;
+            if constexpr (!BL) uo[uu] = valid ? p.u[row] : 0.0f;
+        }
+        if constexpr (BL) {
+            const int64_t r = rb + lane;
+            const float uv = (lane < U * RW && r < row1) ? p.u[r] : 0.0f;
+#pragma unroll
+            for (int uu = 0; uu < U; ++uu) uo[uu] = __shfl(uv, uu * RW + rs, 64);
         }
     };
     auto use = [&](float (&a)[U][CP][C], const float (&uo)[U], int64_t rb) {
+        float unv[U];
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
@@ -601,23 +615,36 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
                 }
             dot = group_sum<LR>(dot);
             const float un = valid ? __builtin_fmaf(-coef, uo[uu], dot) : 0.0f;
-            if (valid && cl == 0) p.u[row] = un;
+            if constexpr (!BL)
+                if (valid && cl == 0) p.u[row] = un;
             if (cl == 0) ss = __builtin_fmaf(un, un, ss);
 #pragma unroll
             for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
                 for (int e = 0; e < C; ++e) g[pp][e] = __builtin_fmaf(un, a[uu][pp][e], g[pp][e]);
+            unv[uu] = un;
+        }
+        if constexpr (BL) {
+            // row l of the block (slot l / RW, row slot l % RW): lane (l % RW) * LR + l / RW
+            // holds its value once each lane has picked un[cl] (cl < U)
+            float v = unv[0];
+#pragma unroll
+            for (int uu = 1; uu < U; ++uu) v = cl == uu ? unv[uu] : v;
+            const int l = lane & (U * RW - 1);
+            const float o = __shfl(v, (l % RW) * LR + l / RW, 64);
+            const int64_t r = rb + lane;
+            if (lane < U * RW && r < row1) p.u[r] = o;
         }
     };
-    int64_t rb = row0 + (int64_t)wave * RW;
+    int64_t rb = row0 + (int64_t)wave * (BL ? U * RW : RW);
     if (rb < row1) load(aA, uA, rb);
     while (rb < row1) {
-        int64_t nx = rb + U * step;
+        int64_t nx = rb + wstride;
         if (nx < row1) load(aB, uB, nx);
         use(aA, uA, rb);
         if (nx >= row1) break;
         rb = nx;
-        nx = rb + U * step;
+        nx = rb + wstride;
         if (nx < row1) load(aA, uA, nx);
         use(aB, uB, rb);
         if (nx >= row1) break;
