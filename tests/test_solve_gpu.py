@@ -124,7 +124,9 @@ def test_solve_small_matches_oracle(rounding, dtype):
                                            (5000, 3, 12, 1, np.float32),      # CountSketch, tiny n
                                            (65536, 130, 520, 4, np.float16),  # 17 chunks per row
                                            (30000, 300, 1200, 4, np.float32),  # two chunks per lane
-                                           (20000, 520, 2080, 4, np.float32)])  # four chunks per lane
+                                           (20000, 520, 2080, 4, np.float32),  # four chunks per lane
+                                           (30000, 100, 400, 4, np.float16),   # 16 lanes a row, 16-row u blocks
+                                           (20000, 12, 48, 4, np.float16)])    # 2 lanes a row: u row by row
 def test_solve_shapes(m, n, d, s, dtype):
     A, b, _, x, info = _solve_case(m, n, d, s, ACC_F16_RN if dtype == np.float16 else ACC_F32, dtype)
     assert info["converged"] == 1, info
