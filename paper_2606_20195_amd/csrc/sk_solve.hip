@@ -910,8 +910,9 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
 // Register-resident panel factorisation for panels of at most 4 * kPT rows:
 // thread t holds rows t, t + kPT, ... (R of them) of the nb <= 32 panel
 // columns in registers.  Step j needs one block reduction: with
-// S_c = sum_{r > j} y_rj y_rc for every column c, S_j is the norm below the
-// diagonal that fixes beta, tau and scal = 1 / (x0 - beta) (x0 = y_jj), and
+// S_c = sum_{r > j} y_rj y_rc for every column c, S_j is the squared norm
+// below the diagonal that fixes beta, tau and scal = 1 / (x0 - beta)
+// (x0 = y_jj), and
 // w_c = y_jc + scal S_c is v_j . y_c for c > j (the dot product of the
 // trailing column with the reflector v_j = (1, scal * y_{r > j, j})) and
 // v_c . v_j for c < j (the Gram column of T).  The update
