@@ -10,15 +10,19 @@ rounding rules).
 Reading adopted by this library (the paper's per-contribution FP16 scheme
 loses about 2% at a 4M-row input, far above a 4e-3 budget): rows are cut into
 consecutive *units* of `chunk_rows` rows; inside a unit the contributions are
-summed in FP32; the unit's partial P_u is then scaled by c_s = fl32(1/sqrt(s))
-and, in the FP16 modes, quantised once per entry with the rounding rule and
-added into the FP16 result with round-to-nearest FP16 additions.  In FP32 mode
-the partials are added in FP32 and c_s is applied once to the total.
+summed in fixed point (`work_item_partial` below: per column an exponent from
+a sample of the unit's first rows, contributions rounded to a grid of
+2**(E_c + h - 19) below 2**(E_c + 1), the rare larger ones kept in FP32 and
+added after the exact fixed-point sum is rounded to FP32); the unit's partial
+P_u is then scaled by c_s = fl32(1/sqrt(s)) and, in the FP16 modes, quantised
+once per entry with the rounding rule and added into the FP16 result with
+round-to-nearest FP16 additions.  In FP32 mode the partials are added in FP32
+and c_s is applied once to the total.
 
 Both orders of summation (inside a unit and across units) are unspecified on
 the GPU; the model fixes unit order.  Results therefore agree exactly when
-every sum is exact (integer-valued A, a single unit per entry, ...) and to a
-tolerance otherwise.
+every sum is exact or one unit covers the rows (one quantisation per entry)
+and each entry receives at most one outlier, and to a tolerance otherwise.
 
 Rounding-noise stream (the paper calls an unspecified random_uint(), Section
 4.2): for the entry (b, c) of the unit whose first global row is r0,
@@ -97,11 +101,133 @@ def unit_partials(A, d, s, seed, chunk_rows, row_offset=0):
     return out
 
 
-def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=None):
+# Fixed-point accumulation of one work item (unit x 32-column tile x group of
+# block_group SparseStack blocks), as the apply kernel computes it.
+LIST_CAP = 1024        # outlier records per work item
+SAMPLE_RANK = 4        # rank of the lane maximum that sets a column's exponent
+HEADROOM = 2           # binades of the exponent above that lane maximum
+TILE_COLS = 32
+WAVE_ROWS = 64
+
+
+def binade(v):
+    """floor(log2 v) for v > 0, elementwise; -1000 for v == 0."""
+    v = np.asarray(v, dtype=np.float64)
+    _, e = np.frexp(v)
+    return np.where(v > 0, e.astype(np.int64) - 1, -1000)
+
+
+def default_plan(s):
+    """(block_group, waves) the planner picks when a block group fits in LDS."""
+    bg = next(b for b in (8, 4, 2, 1) if s % b == 0)
+    return bg, (16 if bg >= 8 else 8)
+
+
+def work_item_partial(X, bk, sg, W, waves, dual):
+    """Unscaled FP32 partial of one work item.
+
+    X: the unit's rows of the tile's live columns as stored values upcast
+    exactly (R x C, C <= 32, float64); bk, sg: bucket offsets within each
+    block (R x BG, in [0, W)) and signs (+-1) of the rows for the group's
+    blocks; waves: waves per workgroup; dual: the FP32 mode's two fields.
+    Returns (P, h, n_out, redone): P is BG*W x C float32 (block-major).
+
+    1. Sample: lane (k, slot) of wave w sees rows 64w + 4g + k, g < 16, of the
+       unit's first 64*waves rows; its largest |x| per column is one sample
+       value, and E_c = binade(4th largest of the 4*waves values) + 2.
+    2. A contribution with |x| >= 2**(E_c + 1) is an outlier; the others are
+       rounded to q = rne(x * 2**S_c), S_c = 19 - h - E_c (E_c clamped to
+       [-108 - h, 145 - h]); the FP32 mode adds the residual's
+       z = rne((x * 2**S_c - q) * 2**21) at 2**(S_c + 21).
+    3. If more than LIST_CAP outlier records (elements x BG) arise, E_c
+       becomes binade(max |x| of the column); if a bucket row takes
+       K >= 2**(10 + h) contributions, h grows; the item is then recomputed.
+    4. P = fl32(exact signed sum * 2**-S_c), then each outlier sign * x is
+       added in FP32 (rows in order).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    R, C = X.shape
+    bg = bk.shape[1]
+    if not np.all(np.isfinite(X)):
+        raise ValueError("non-finite input takes the float path; not modelled")
+    absX = np.abs(X)
+    rows = WAVE_ROWS * waves
+    Xs = np.zeros((rows, C))
+    Xs[:min(R, rows)] = absX[:rows]
+    lane_max = Xs.reshape(waves, 16, 4, C).max(axis=1).reshape(4 * waves, C)
+    M = -np.sort(-lane_max, axis=0)[SAMPLE_RANK - 1]
+    E = binade(M) + HEADROOM
+    kall = max(int(np.bincount(bk[:, j], minlength=W).max()) if R else 0 for j in range(bg))
+    h = 0
+    redone = False
+    for attempt in range(2):
+        Ec = np.clip(E, -108 - h, 145 - h)
+        thr = np.ldexp(1.0, Ec + 1)
+        out = absX >= thr[None, :]
+        n_out = int(out.sum()) * bg
+        if kall < (1 << (10 + h)) and n_out <= LIST_CAP:
+            break
+        if attempt == 1:
+            raise AssertionError("the second attempt always succeeds")
+        redone = True
+        if n_out > LIST_CAP:
+            E = binade(absX.max(axis=0) if R else np.zeros(C))
+        while kall >= (1 << (10 + h)):
+            h += 1
+    S = 19 - h - Ec
+    scaled = np.where(out, 0.0, X) * np.ldexp(1.0, S)[None, :]
+    q = np.rint(scaled)
+    if dual:
+        z = np.rint((scaled - q) * 2.0 ** 21)
+        val = q.astype(np.int64) * (1 << 21) + z.astype(np.int64)
+        shift = S + 21
+    else:
+        val = q.astype(np.int64)
+        shift = S
+    acc = np.zeros((bg * W, C), dtype=np.int64)
+    for j in range(bg):
+        np.add.at(acc, j * W + bk[:, j], sg[:, j:j + 1].astype(np.int64) * val)
+    if dual:
+        P = (acc.astype(np.float64) * np.ldexp(1.0, -shift)[None, :]).astype(np.float32)
+    else:
+        P = (acc.astype(np.float32).astype(np.float64) * np.ldexp(1.0, -shift)[None, :]).astype(np.float32)
+    for i, c in zip(*np.nonzero(out)):
+        for j in range(bg):
+            e = j * W + bk[i, j]
+            P[e, c] = np.float32(P[e, c] + np.float32(sg[i, j] * X[i, c]))
+    return P, h, n_out, redone
+
+
+def unit_partial_fixed(A, d, s, seed, r0, waves=None, block_group=None, dual=False):
+    """Unscaled FP32 partial (d x n) of one unit of rows A (first global row
+    r0), assembled from its work items."""
+    from .sketch import hash_rows
+    check_shape(d, s)
+    bgd, wd = default_plan(s)
+    bg = block_group or bgd
+    waves = waves or wd
+    A = np.asarray(A)
+    R, n = A.shape
+    W = d // s
+    b, g = hash_rows(seed, np.arange(R, dtype=np.uint64) + np.uint64(r0), d, s)
+    off = b - (np.arange(s, dtype=np.int64) * W)[None, :]
+    X = A.astype(np.float64)
+    P = np.zeros((d, n), dtype=np.float32)
+    for j0 in range(0, s, bg):
+        for c0 in range(0, n, TILE_COLS):
+            c1 = min(c0 + TILE_COLS, n)
+            Pi, _, _, _ = work_item_partial(X[:, c0:c1], off[:, j0:j0 + bg], g[:, j0:j0 + bg], W, waves, dual)
+            P[j0 * W:(j0 + bg) * W, c0:c1] = Pi
+    return P
+
+
+def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=None, waves=None,
+                    block_group=None):
     """FP16-mode result, units added in order.
 
-    Each unit partial is taken as fl32 of its exact value (exact for integer
-    A with |sums| < 2**24), scaled by c_s32 in FP32, quantised per entry with
+    Each unit partial is `unit_partial_fixed` (the exact sum when every
+    contribution sits on its column's grid, e.g. integer A with
+    |sums| < 2**24), scaled by c_s32 in FP32, quantised per entry with
     rounding `mode` and noise from round_u24, then added with FP16 RN adds.
     """
     check_shape(d, s)
@@ -112,14 +238,24 @@ def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=No
     cs = c_s32(s)
     site = (np.arange(d, dtype=np.uint64)[:, None] * np.uint64(n)
             + np.arange(n, dtype=np.uint64)[None, :])
-    for r0, P in unit_partials(A, d, s, seed, chunk_rows, row_offset):
-        v = (cs * P.astype(np.float32)).astype(np.float32)
+    for a, b in units(A.shape[0], chunk_rows):
+        r0 = row_offset + a
+        P = unit_partial_fixed(A[a:b], d, s, seed, r0, waves, block_group)
+        v = (cs * P).astype(np.float32)
         u = None
         if mode in (ACC_F16_SR, ACC_F16_DITHER):
             u = round_u24(seed, epoch, np.uint64(r0) * np.uint64(d * n) + site)
         qv = quantize(mode, v, u)
         acc = f16_add(acc, qv)
     return acc
+
+
+def apply_f32_one_unit_model(A, d, s, seed, row_offset=0, waves=None, block_group=None):
+    """FP32-mode result when one unit covers the rows: fl32(c_s32 * P) with P
+    the two-field fixed-point partial (c_s32 is applied to the FP32 partial,
+    exactly, when it is a power of two, else once to the FP32 total)."""
+    P = unit_partial_fixed(A, d, s, seed, row_offset, waves, block_group, dual=True)
+    return (c_s32(s) * P).astype(np.float32)
 
 
 def contribution_sites(rows, j, n, s):

@@ -127,13 +127,16 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         pl.chunk_rows = f->chunk_rows;
         if (pl.chunk_rows > max_chunk)
             return set_error(SK_EUNSUPPORTED, "chunk_rows = %d spans more than 2 GiB", pl.chunk_rows);
+        if (pl.chunk_rows > kMaxChunkRows)
+            return set_error(SK_EINVAL, "chunk_rows = %d exceeds %d (16-bit per-bucket counts)", pl.chunk_rows,
+                             kMaxChunkRows);
     } else {
         const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)(dev.lds_max / pl.lds_bytes));
         const int64_t target = std::max<int64_t>(1, (int64_t)dev.cus * wg_per_cu / per_unit);
         int64_t chunk = (rows + target - 1) / target;
         chunk = (chunk + 63) / 64 * 64;
         chunk = std::max<int64_t>(chunk, 2048);
-        chunk = std::min<int64_t>(chunk, max_chunk);
+        chunk = std::min<int64_t>(std::min<int64_t>(chunk, max_chunk), kMaxChunkRows);
         pl.chunk_rows = (int32_t)chunk;
     }
     pl.units = rows > 0 ? (rows + pl.chunk_rows - 1) / pl.chunk_rows : 0;
@@ -146,8 +149,8 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
 
 static int check_schedule(const sk_schedule* s)
 {
-    if (s->chunk_rows < 0 || s->chunk_rows % 64)
-        return set_error(SK_EINVAL, "chunk_rows must be a non-negative multiple of 64");
+    if (s->chunk_rows < 0 || s->chunk_rows % 64 || s->chunk_rows > kMaxChunkRows)
+        return set_error(SK_EINVAL, "chunk_rows must be a multiple of 64 in 0..%d", kMaxChunkRows);
     if (s->block_group && s->block_group != 1 && s->block_group != 2 && s->block_group != 4 && s->block_group != 8)
         return set_error(SK_EINVAL, "block_group must be 0, 1, 2, 4 or 8");
     if (s->waves && s->waves != 4 && s->waves != 8 && s->waves != 16)

@@ -161,24 +161,44 @@ __device__ __forceinline__ void static_for(F&& f)
 template <typename AT>
 constexpr int kMaxThreads = sizeof(AT) == 4 ? 512 : 1024;
 
-// Fixed-point LDS partials (the FP16 modes).
+// Fixed-point LDS partials.
 //
-// LDS floating-point atomics are two orders of magnitude slower than integer
-// ones on this GPU, so the FP16 modes accumulate each unit exactly in integer
-// fixed point: a contribution x becomes q = round(x * 2^S) with |q| < 2^(20-c)
-// and is added as the offset-binary field B + sigma*q (B = 2^(21-c)) into one
-// 32-bit half of a 64-bit LDS word; the two columns of a lane's pair share
-// one ds_add_u64.  The conversion is a single FMA, y = x * 2^S + 2^23 + B,
-// whose low 23 bits are B + q; XOR with 0x4B000000 (sign +) or
-// 0x4B000000 | (2B - 1) (sign -) turns y's bits into the field value, the
-// negative case being B - q - 1.  A per-bucket-row counter holds the number
-// K of contributions (low 16 bits) and of negative ones N (high 16 bits), so
-// the field sum F decodes exactly to sum(sigma*q) = F - K*B + N as long as no
-// field exceeds 2^32 (K < 2^(10+c)).  S comes from the largest |x| of the
-// first tiles (one binade of headroom); the workgroup tracks the true maximum
-// and the largest K and, if either bound was broken, recomputes the unit with
-// the exact parameters.  Non-finite input falls back to FP32 LDS atomics.
+// LDS floating-point atomics run at about 1/25 of the rate of 64-bit integer
+// atomics on this GPU (ds_add_f32 and ds_pk_add_f16 take about 190 clocks per
+// wave instruction, ds_add_u64 about 8), so each unit is accumulated exactly
+// in integer fixed point.  Column c of a work item has its own exponent E_c:
+// a contribution x with |x| < 2^(E_c+1) becomes q = rne(x * 2^S_c),
+// S_c = 19 - h - E_c, |q| <= 2^(20-h), and is added as the offset-binary
+// field B + sigma*q (B = 2^(21-h)) into one 32-bit half of a 64-bit LDS word;
+// the two columns of a lane's pair share one ds_add_u64.  The conversion is a
+// single FMA, y = x * 2^S_c + 2^23 + B, whose low 23 bits are B + q; XOR with
+// 0x4B000000 (sign +) or 0x4B000000 | (2B - 1) (sign -) turns y's bits into
+// the field value, the negative case being B - q - 1.  A per-bucket-row
+// counter holds the number K of contributions (low 16 bits) and of negative
+// ones N (high 16 bits), so the field sum F decodes exactly to
+// sum(sigma*q) = F - K*B + N as long as no field exceeds 2^32 (K < 2^(10+h);
+// the count headroom h is 0 unless a bucket row takes 1024 or more
+// contributions in one unit; the planner keeps units below 65536 rows so K
+// and N fit their 16 bits).
+//
+// E_c comes from a sample, the first 64-row tile of every wave: each lane's
+// largest |x| in the column over its 16 rows of that tile, and
+// E_c = binade(4th largest of those lane maxima) + 2.  A contribution with
+// |x| >= 2^(E_c+1) (an outlier: a few rows far above the rest of their
+// column, such as identity rows stacked on a small dense block) adds zero to
+// the field and is appended instead, as (LDS entry, sign * x), to a list in
+// LDS; the list is added to the decoded FP32 partial before the flush.  If the
+// list overflows, the unit is recomputed with E_c = binade of the column's
+// true maximum (then no contribution is an outlier); if a bucket row breaks
+// the K bound, with a larger h.  Non-finite input falls back to FP32 LDS
+// atomics.
 constexpr uint32_t kMagicBits = 0x4B000000u;   // bit pattern of 2^23
+constexpr int kListCap = 1024;                 // outlier records per work item
+constexpr int kSampleRank = 4;                 // rank of the lane maximum that sets E_c
+constexpr int kHeadroom = 2;                   // binades of E_c above that lane maximum
+constexpr int kCtlWords = 8 + 2 * kNT;         // control words, per-column S, per-column maximum
+constexpr int kAuxWords = 2 * kListCap;        // the outlier list; before the pass, the sample
+static_assert(kAuxWords >= 16 * 4 * kNT, "the sample of 16 waves must fit the list area");
 
 template <int BG>
 __device__ __forceinline__ uint32_t lds_row_fixed(uint32_t lb, uint32_t o, uint32_t W)
@@ -188,11 +208,16 @@ __device__ __forceinline__ uint32_t lds_row_fixed(uint32_t lb, uint32_t o, uint3
     return BG == 1 ? o * kNT : (lb >> 1) * (W * 64u + 64u) + o * 64u + 32u * (lb & 1u);
 }
 
-// Largest |x| of one lane's pair so far, as sign-cleared bit patterns (monotone
-// in |x|; infinities and NaNs compare above every finite value).
-__device__ __forceinline__ uint32_t pair_mag(const PairRaw<float>& r, uint32_t m)
+// Largest |x| of each column of one lane's pair, as sign-cleared bit patterns
+// in the element format (monotone in |x|; infinities and NaNs compare above
+// every finite value).  FP32: one word per column; 16-bit types: the two
+// 16-bit magnitudes packed in one word.
+template <typename AT> struct MagOf { typedef uint32_t type; };
+template <> struct MagOf<float> { typedef uint2 type; };
+
+__device__ __forceinline__ uint2 pair_mag(const PairRaw<float>& r, uint2 m)
 {
-    return max(m, max(__float_as_uint(r.v.x) & 0x7FFFFFFFu, __float_as_uint(r.v.y) & 0x7FFFFFFFu));
+    return make_uint2(max(m.x, __float_as_uint(r.v.x) & 0x7FFFFFFFu), max(m.y, __float_as_uint(r.v.y) & 0x7FFFFFFFu));
 }
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 template <typename AT>
@@ -213,51 +238,132 @@ __device__ __forceinline__ uint32_t pair_mag<__half>(const PairRaw<__half>& r, u
                  : "=v"(out) : "v"(m), "v"(r.v));
     return out;
 }
-__device__ __forceinline__ uint32_t mag16_to_f32bits(uint32_t m, bool bf16)
+__device__ __forceinline__ uint2 mag_max(uint2 a, uint2 b) { return make_uint2(max(a.x, b.x), max(a.y, b.y)); }
+__device__ __forceinline__ uint32_t mag_max(uint32_t a, uint32_t b)
 {
-    const uint32_t a = max(m & 0xFFFFu, m >> 16);
-    if (bf16) return a << 16;
-    return __float_as_uint(__half2float(__ushort_as_half((unsigned short)a)));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+// true if either column's magnitude reaches its threshold
+__device__ __forceinline__ bool mag_reaches(uint2 m, uint2 t) { return m.x >= t.x || m.y >= t.y; }
+__device__ __forceinline__ bool mag_reaches(uint32_t m, uint32_t t)
+{
+    return (m & 0xFFFFu) >= (t & 0xFFFFu) || (m >> 16) >= (t >> 16);
 }
 
-struct FixedParams {
-    float scale;      // 2^S
-    float magic;      // 2^23 + B
-    uint32_t xneg;    // 0x4B000000 | (2B - 1)
+// The two columns' magnitudes as FP32 magnitude bits.
+template <typename AT>
+__device__ __forceinline__ void mag_cols(uint32_t m, uint32_t& a, uint32_t& b)
+{
+    if constexpr (std::is_same<AT, __hip_bfloat16>::value) {
+        a = (m & 0xFFFFu) << 16;
+        b = m & 0xFFFF0000u;
+    } else {
+        a = __float_as_uint(__half2float(__ushort_as_half((unsigned short)(m & 0xFFFFu))));
+        b = __float_as_uint(__half2float(__ushort_as_half((unsigned short)(m >> 16))));
+    }
+}
+template <typename AT>
+__device__ __forceinline__ void mag_cols(uint2 m, uint32_t& a, uint32_t& b)
+{
+    a = m.x;
+    b = m.y;
+}
+
+// floor(log2 v) of a finite FP32 magnitude given as bits (subnormals exact);
+// -1000 for zero, 128 for infinities and NaNs.
+__device__ __forceinline__ int binade_exact(uint32_t b)
+{
+    if (b == 0) return -1000;
+    const int e = (int)(b >> 23);
+    if (e) return e - 127;
+    return (31 - __clz((int)b)) - 149;
+}
+
+// Magnitude bits, in the element format, of 2^e (e clamped to the format's
+// range: beyond the largest finite value every finite magnitude is below it,
+// below the smallest subnormal every nonzero magnitude reaches it).
+template <typename AT>
+__device__ __forceinline__ uint32_t pow2_bits(int e)
+{
+    if constexpr (sizeof(AT) == 4) {
+        if (e > 127) return 0x7F800000u;
+        if (e < -149) return 1u;
+        if (e < -126) return 1u << (e + 149);
+        return (uint32_t)(e + 127) << 23;
+    } else if constexpr (std::is_same<AT, __hip_bfloat16>::value) {
+        if (e > 127) return 0x7F80u;
+        if (e < -133) return 1u;
+        if (e < -126) return 1u << (e + 133);
+        return (uint32_t)(e + 127) << 7;
+    } else {
+        if (e > 15) return 0x7C00u;
+        if (e < -24) return 1u;
+        if (e < -14) return 1u << (e + 24);
+        return (uint32_t)(e + 15) << 10;
+    }
+}
+
+// Per-lane fixed-point parameters of one attempt.
+template <typename AT>
+struct Fixed {
+    float slo, shi;                   // 2^S of the lane's two columns
+    typename MagOf<AT>::type thr;     // outlier thresholds 2^(E+1), element format
+    float magic;                      // 2^23 + B
+    uint32_t xneg;                    // 0x4B000000 | (2B - 1)
     uint32_t B;
-    int S;
+    int Slo, Shi;
 };
 
-__device__ __forceinline__ FixedParams fixed_params(int E, int c)
+__device__ __forceinline__ int clamp_exponent(int E, int h)
 {
-    FixedParams f;
-    int S = 19 - c - E;
-    S = S > 127 ? 127 : (S < -126 ? -126 : S);
-    f.S = S;
-    f.scale = __uint_as_float((uint32_t)(S + 127) << 23);
-    f.B = 1u << (21 - c);
+    // keeps S = 19 - h - E a normal FP32 exponent
+    return max(min(E, 145 - h), -108 - h);
+}
+
+template <typename AT>
+__device__ __forceinline__ Fixed<AT> fixed_params(int Elo, int Ehi, int h)
+{
+    Fixed<AT> f;
+    Elo = clamp_exponent(Elo, h);
+    Ehi = clamp_exponent(Ehi, h);
+    f.Slo = 19 - h - Elo;
+    f.Shi = 19 - h - Ehi;
+    f.slo = __uint_as_float((uint32_t)(f.Slo + 127) << 23);
+    f.shi = __uint_as_float((uint32_t)(f.Shi + 127) << 23);
+    if constexpr (sizeof(AT) == 4) f.thr = make_uint2(pow2_bits<AT>(Elo + 1), pow2_bits<AT>(Ehi + 1));
+    else f.thr = pow2_bits<AT>(Elo + 1) | (pow2_bits<AT>(Ehi + 1) << 16);
+    f.B = 1u << (21 - h);
     f.magic = 8388608.0f + (float)f.B;
     f.xneg = kMagicBits | (2u * f.B - 1u);
     return f;
 }
 
-__device__ __forceinline__ int binade_of(uint32_t magbits)
+// Whether each element of a pair is an outlier (magnitude bits >= threshold).
+__device__ __forceinline__ void elem_out(const PairRaw<float>& r, uint2 t, bool& olo, bool& ohi)
 {
-    if (magbits == 0) return 0;
-    const int e = (int)((magbits >> 23) & 0xFFu) - 127;
-    return e < -126 ? -126 : e;
+    olo = (__float_as_uint(r.v.x) & 0x7FFFFFFFu) >= t.x;
+    ohi = (__float_as_uint(r.v.y) & 0x7FFFFFFFu) >= t.y;
+}
+template <typename AT>
+__device__ __forceinline__ void elem_out(const PairRaw<AT>& r, uint32_t t, bool& olo, bool& ohi)
+{
+    olo = (r.v & 0x7FFFu) >= (t & 0xFFFFu);
+    ohi = ((r.v >> 16) & 0x7FFFu) >= (t >> 16);
 }
 
 // ACC: 0 = FP32 LDS atomics, 1 = one fixed-point field per element (FP16
 // modes), 2 = two fields per element (FP32 mode): the rounded value and its
 // residual at 2^-21 finer resolution, kept in two LDS arrays with the same
-// layout, so each unit is summed with about 41 significant bits.
+// layout, so each unit is summed with about 41 significant bits below
+// 2^(E_c+1).
 // One work item: the partial sketch of unit `unit` (rows [unit * chunk_rows,
 // ...)), column tile `ct` and block group `bgi`, accumulated in LDS and added
 // into SA.  Called by every thread of the workgroup; ends with LDS free.
 template <typename AT, int BG, bool VEC, int ACC>
 __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct, int bgi, float* lds)
 {
+    typedef typename MagOf<AT>::type Mag;
     const int nwaves = (int)(blockDim.x >> 6);
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
@@ -269,7 +375,10 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     const size_t nw = lds_words<BG>(W);
     const size_t narr = (ACC == 2) ? 2 : 1;       // fixed-point arrays
     uint32_t* cnt = (uint32_t*)lds + narr * nw;   // per bucket row, K | N << 16
-    uint32_t* ctl = cnt + (size_t)BG * W;         // [0] first max, [1] max, [2] max K
+    uint32_t* ctl = cnt + (size_t)BG * W;         // [0] outliers, [1] non-finite, [2] max K
+    int* colS = (int*)ctl + 8;                    // per column: E (sample), then S
+    uint32_t* colmax = ctl + 8 + kNT;             // per column: largest |x| (FP32 bits)
+    uint32_t* aux = ctl + kCtlWords;              // sample, then outlier list
     const uint32_t lo_off = (uint32_t)(nw * 4);   // byte offset of the residual array
 
     const int k = lane >> 4;                 // row slot within a wave instruction
@@ -279,6 +388,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     // add lands in LDS columns >= n, which are never flushed.
     const int colc = (col < p.n) ? col : 0;
     const uint32_t d1 = (colc + 1 < p.n) ? 1u : 0u;
+    const bool live_lo = col < p.n, live_hi = col + 1 < p.n;
     const uint32_t laneoff = (uint32_t)(2 * q) * 4u;
     const int64_t span = r_end - r_begin;
     const int64_t ntiles = span > 0 ? (span + kTile - 1) / kTile : 0;
@@ -295,9 +405,11 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     const uint32_t gstep = 4u * (uint32_t)p.lda * esz;
     const uint32_t tstep = (uint32_t)kTile * (uint32_t)p.lda * esz;
 
+    // Clears the partial (and, with the fixed-point arrays, the counters and
+    // control words).
     auto zero_lds = [&](bool with_counters) {
         const size_t base = with_counters ? narr * nw : nw;
-        const size_t words = base + (with_counters ? (size_t)BG * W + 4 : 0);
+        const size_t words = base + (with_counters ? (size_t)BG * W + kCtlWords : 0);
         float4* l4 = (float4*)lds;
         for (size_t e = threadIdx.x; e < base / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
         for (size_t e = base + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
@@ -309,7 +421,8 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         for (int g = 0; g < kGroups; ++g) buf[g] = load_pair<VEC, AT>(rsrc, vo, (uint32_t)g * gstep, d1);
     };
 
-    auto tile_mag = [&](const PairRaw<AT> (&buf)[kGroups], uint32_t m) {
+    auto tile_mag = [&](const PairRaw<AT> (&buf)[kGroups]) {
+        Mag m{};
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) m = pair_mag(buf[g], m);
         return m;
@@ -369,51 +482,72 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         });
     };
 
-    auto scatter_fixed = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
-                             const uint32_t (&hsgn)[BG], float scale, float magic) {
-        static_for<0, kGroups>([&](auto gc) {
-            constexpr int g = decltype(gc)::value;
-            float lo, hi;
-            to_f32(buf[g], lo, hi);
-            const uint32_t ylo = __float_as_uint(__builtin_fmaf(lo, scale, magic));
-            const uint32_t yhi = __float_as_uint(__builtin_fmaf(hi, scale, magic));
-#pragma unroll
-            for (int jj = 0; jj < BG; ++jj) {
-                const uint32_t off = bcast16<g>(hoff[jj]) + laneoff;
-                const uint32_t x = bcast16<g>(hsgn[jj]);
-                const uint64_t v = ((uint64_t)(yhi ^ x) << 32) | (uint64_t)(ylo ^ x);
-                unsigned long long* dst = (unsigned long long*)__builtin_assume_aligned((char*)lds + off, 8);
-                __hip_atomic_fetch_add(dst, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        });
+    // Appends an outlier record: word index of the entry in array 0, signed value.
+    auto push_outlier = [&](uint32_t word, float v) {
+        const uint32_t i = __hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (i < (uint32_t)kListCap) {
+            aux[2 * i] = word;
+            aux[2 * i + 1] = __float_as_uint(v);
+        }
     };
 
-    // Two fields per element: y = x*2^S + (2^23 + B) rounds x*2^S to an integer
-    // Q = y - 2^23 - B, the FMA x*2^S - Q is the exact residual (|r| <= 1/2),
-    // and z = r*2^21 + (2^23 + B) is its fixed-point form.
-    auto scatter_dual = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
-                            const uint32_t (&hsgn)[BG], float scale, float magic) {
+    // Fixed-point scatter of one tile.  ACC == 1: y = x*2^S + (2^23 + B) is the
+    // field.  ACC == 2: y rounds x*2^S to an integer Q = y - 2^23 - B, the FMA
+    // x*2^S - Q is the exact residual (|r| <= 1/2), and z = r*2^21 + (2^23 + B)
+    // is its field in the second array.  OUT: the tile holds an outlier in some
+    // lane; outliers add zero and go to the list.
+    auto scatter_fixed = [&](const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                             const uint32_t (&hsgn)[BG], const Fixed<AT>& fx, auto out_tag) {
+        constexpr bool OUT = decltype(out_tag)::value;
         static_for<0, kGroups>([&](auto gc) {
             constexpr int g = decltype(gc)::value;
             float lo, hi;
             to_f32(buf[g], lo, hi);
-            const float ylo = __builtin_fmaf(lo, scale, magic);
-            const float yhi = __builtin_fmaf(hi, scale, magic);
-            const float rlo = __builtin_fmaf(lo, scale, -(ylo - magic));
-            const float rhi = __builtin_fmaf(hi, scale, -(yhi - magic));
-            const uint32_t zlo = __float_as_uint(__builtin_fmaf(rlo, 2097152.0f, magic));
-            const uint32_t zhi = __float_as_uint(__builtin_fmaf(rhi, 2097152.0f, magic));
+            bool olo = false, ohi = false;
+            if constexpr (OUT) {
+                elem_out(buf[g], fx.thr, olo, ohi);
+                if (olo) lo = 0.0f;
+                if (ohi) hi = 0.0f;
+            }
+            const float ylo = __builtin_fmaf(lo, fx.slo, fx.magic);
+            const float yhi = __builtin_fmaf(hi, fx.shi, fx.magic);
+            uint32_t zlo = 0, zhi = 0;
+            if constexpr (ACC == 2) {
+                const float rlo = __builtin_fmaf(lo, fx.slo, -(ylo - fx.magic));
+                const float rhi = __builtin_fmaf(hi, fx.shi, -(yhi - fx.magic));
+                zlo = __float_as_uint(__builtin_fmaf(rlo, 2097152.0f, fx.magic));
+                zhi = __float_as_uint(__builtin_fmaf(rhi, 2097152.0f, fx.magic));
+            }
             const uint32_t alo = __float_as_uint(ylo), ahi = __float_as_uint(yhi);
 #pragma unroll
             for (int jj = 0; jj < BG; ++jj) {
                 const uint32_t off = bcast16<g>(hoff[jj]) + laneoff;
                 const uint32_t x = bcast16<g>(hsgn[jj]);
                 const uint64_t v = ((uint64_t)(ahi ^ x) << 32) | (uint64_t)(alo ^ x);
-                const uint64_t w = ((uint64_t)(zhi ^ x) << 32) | (uint64_t)(zlo ^ x);
                 unsigned long long* dst = (unsigned long long*)__builtin_assume_aligned((char*)lds + off, 8);
-                unsigned long long* dst2 = (unsigned long long*)__builtin_assume_aligned((char*)lds + off + lo_off, 8);
                 __hip_atomic_fetch_add(dst, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(dst2, (unsigned long long)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if constexpr (ACC == 2) {
+                    const uint64_t w = ((uint64_t)(zhi ^ x) << 32) | (uint64_t)(zlo ^ x);
+                    unsigned long long* dst2 =
+                        (unsigned long long*)__builtin_assume_aligned((char*)lds + off + lo_off, 8);
+                    __hip_atomic_fetch_add(dst2, (unsigned long long)w, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+            if constexpr (OUT) {
+                const bool rlo = olo && live_lo, rhi = ohi && live_hi;
+                if (__builtin_amdgcn_ballot_w64(rlo || rhi) != 0) {
+                    float vlo, vhi;
+                    to_f32(buf[g], vlo, vhi);
+#pragma unroll
+                    for (int jj = 0; jj < BG; ++jj) {
+                        // broadcasts with every lane active, then the per-lane pushes
+                        const uint32_t word = (bcast16<g>(hoff[jj]) + laneoff) >> 2;
+                        const bool neg = bcast16<g>(hsgn[jj]) != kMagicBits;
+                        if (rlo) push_outlier(word, neg ? -vlo : vlo);
+                        if (rhi) push_outlier(word + 1u, neg ? -vhi : vhi);
+                    }
+                }
             }
         });
     };
@@ -421,16 +555,34 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     PairRaw<AT> bufA[kGroups], bufB[kGroups];
     uint32_t offA[BG], sgnA[BG], offB[BG], sgnB[BG];
 
-    // Stream the unit once; `fixed` selects the accumulation.  bufA holds the
-    // wave's first tile on entry when `preloaded`.  Returns the lane's largest
-    // input magnitude bits.
-    auto run = [&](int acc, bool preloaded, const FixedParams& fp) {
+    // One tile: fixed point (with the outlier path when a lane of the wave
+    // holds one) or float atomics.  Returns the lane's column maxima so far.
+    auto process = [&](int acc, const PairRaw<AT> (&buf)[kGroups], const uint32_t (&hoff)[BG],
+                       const uint32_t (&hsgn)[BG], const Fixed<AT>& fx, Mag mag) {
+        if constexpr (ACC != 0) {
+            if (acc != 0) {
+                const Mag tm = tile_mag(buf);
+                if (__builtin_amdgcn_ballot_w64(mag_reaches(tm, fx.thr)) != 0)
+                    scatter_fixed(buf, hoff, hsgn, fx, std::true_type{});
+                else
+                    scatter_fixed(buf, hoff, hsgn, fx, std::false_type{});
+                return mag_max(mag, tm);
+            }
+        }
+        scatter_float(buf, hoff, hsgn);
+        return mag;
+    };
+
+    // Stream the unit once; `acc` selects the accumulation.  bufA holds the
+    // wave's first tile on entry when `preloaded`.  Returns the lane's column
+    // maxima.
+    auto run = [&](int acc, bool preloaded, const Fixed<AT>& fx) {
         const bool fixed = acc != 0;
-        uint32_t mag = 0;
+        Mag mag{};
         int64_t tile = wave;
         if (tile < ntiles) {
             if (!preloaded) load_tile(bufA, tile);
-            hash_tile(offA, sgnA, tile, fixed, fp.xneg);
+            hash_tile(offA, sgnA, tile, fixed, fx.xneg);
         }
         // Software pipeline: the next tile's loads are in flight while the
         // current tile is scattered; unrolled twice to ping-pong the buffers.
@@ -442,39 +594,15 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         while (tile < ntiles) {
             int64_t nxt = tile + nwaves;
             load_tile(bufB, min(nxt, ntiles));     // tile ntiles lies wholly past the unit
-            if (acc == 2) {
-                if constexpr (ACC == 2) {
-                    mag = tile_mag(bufA, mag);
-                    scatter_dual(bufA, offA, sgnA, fp.scale, fp.magic);
-                }
-            } else if (acc == 1) {
-                if constexpr (ACC == 1) {
-                    mag = tile_mag(bufA, mag);
-                    scatter_fixed(bufA, offA, sgnA, fp.scale, fp.magic);
-                }
-            } else {
-                scatter_float(bufA, offA, sgnA);
-            }
+            mag = process(acc, bufA, offA, sgnA, fx, mag);
             if (nxt >= ntiles) break;
-            hash_tile(offB, sgnB, nxt, fixed, fp.xneg);
+            hash_tile(offB, sgnB, nxt, fixed, fx.xneg);
             tile = nxt;
             nxt = tile + nwaves;
             load_tile(bufA, min(nxt, ntiles));
-            if (acc == 2) {
-                if constexpr (ACC == 2) {
-                    mag = tile_mag(bufB, mag);
-                    scatter_dual(bufB, offB, sgnB, fp.scale, fp.magic);
-                }
-            } else if (acc == 1) {
-                if constexpr (ACC == 1) {
-                    mag = tile_mag(bufB, mag);
-                    scatter_fixed(bufB, offB, sgnB, fp.scale, fp.magic);
-                }
-            } else {
-                scatter_float(bufB, offB, sgnB);
-            }
+            mag = process(acc, bufB, offB, sgnB, fx, mag);
             if (nxt >= ntiles) break;
-            hash_tile(offA, sgnA, nxt, fixed, fp.xneg);
+            hash_tile(offA, sgnA, nxt, fixed, fx.xneg);
             tile = nxt;
         }
         return mag;
@@ -484,68 +612,132 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
         return v;
     };
-    auto to_f32bits = [&](uint32_t m) -> uint32_t {
-        if constexpr (sizeof(AT) == 4) return m;
-        else return mag16_to_f32bits(m, std::is_same<AT, __hip_bfloat16>::value);
-    };
 
     bool fixed_ok = false;
-    FixedParams fp = fixed_params(0, 0);
+    uint32_t nout = 0;            // outlier records to add before the flush
+    uint32_t Bfix = 0;
+    Fixed<AT> fx = fixed_params<AT>(0, 0, 0);
     if constexpr (ACC != 0) {
         zero_lds(true);
-        __syncthreads();
-        // Scale from the first tile of every wave, with one binade of headroom.
-        uint32_t m0 = 0;
+        // The sample: every lane's column maxima over its rows of the wave's
+        // first tile, column-major with L = 4 * nwaves values per column.
+        const int L = 4 * nwaves;
+        Mag m0{};
         if (wave < ntiles) {
             load_tile(bufA, wave);
-            m0 = to_f32bits(tile_mag(bufA, 0u));
+            m0 = tile_mag(bufA);
         }
-        m0 = wave_max(m0);
-        if (lane == 0) atomicMax(&ctl[0], m0);
+        {
+            uint32_t a0, a1;
+            mag_cols<AT>(m0, a0, a1);
+            aux[(2 * q) * L + wave * 4 + k] = a0;
+            aux[(2 * q + 1) * L + wave * 4 + k] = a1;
+        }
         __syncthreads();
-        const uint32_t first = ctl[0];
-        if (first < 0x7F800000u) {
-            int E = binade_of(first) + 1;
-            int c = 0;
-            for (int attempt = 0; attempt < 2 && !fixed_ok; ++attempt) {
-                if (attempt > 0) {
-                    zero_lds(true);
-                    __syncthreads();
+        if (threadIdx.x < (unsigned)kNT) {
+            // the kSampleRank-th largest lane maximum of the column (a sorting network step per value)
+            uint32_t t[kSampleRank] = {};
+            for (int i = 0; i < L; ++i) {
+                uint32_t v = aux[threadIdx.x * L + i];
+#pragma unroll
+                for (int r = 0; r < kSampleRank; ++r) {
+                    const uint32_t a = max(t[r], v);
+                    v = min(t[r], v);
+                    t[r] = a;
                 }
-                fp = fixed_params(E, c);
-                uint32_t m = to_f32bits(run(ACC, attempt == 0, fp));
-                m = wave_max(m);
-                if (lane == 0) atomicMax(&ctl[1], m);
-                __syncthreads();
-                uint32_t kmax = 0;
-                for (uint32_t e = threadIdx.x; e < (uint32_t)BG * W; e += blockDim.x) kmax = max(kmax, cnt[e] & 0xFFFFu);
-                kmax = wave_max(kmax);
-                if (lane == 0) atomicMax(&ctl[2], kmax);
-                __syncthreads();
-                const uint32_t mall = ctl[1], kall = ctl[2];
-                if (mall >= 0x7F800000u) break;                    // non-finite input
-                const bool mag_ok = binade_of(mall) <= E;          // |x| < 2^(E+1)
-                const bool cnt_ok = kall < (1u << (10 + c));
-                fixed_ok = mag_ok && cnt_ok;
-                if (!fixed_ok) {
-                    E = max(E, binade_of(mall));
-                    while (kall >= (1u << (10 + c))) ++c;
-                }
-                __syncthreads();
-                if (!fixed_ok && threadIdx.x == 0) { ctl[1] = 0; ctl[2] = 0; }
             }
+            colS[threadIdx.x] = binade_exact(t[kSampleRank - 1]) + kHeadroom;
         }
-        if (!fixed_ok) {
+        __syncthreads();
+        int Elo = colS[2 * q], Ehi = colS[2 * q + 1];
+        int h = 0;
+        for (int attempt = 0; attempt < 2 && !fixed_ok; ++attempt) {
+            if (attempt > 0) {
+                zero_lds(true);
+                __syncthreads();
+            }
+            fx = fixed_params<AT>(Elo, Ehi, h);
+            const Mag m = run(ACC, attempt == 0, fx);
+            uint32_t a0, a1;
+            mag_cols<AT>(m, a0, a1);
+            if (a0 >= 0x7F800000u || a1 >= 0x7F800000u) ctl[1] = 1u;
+            if (live_lo) atomicMax(&colmax[2 * q], a0);
+            if (live_hi) atomicMax(&colmax[2 * q + 1], a1);
+            uint32_t kmax = 0;
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < (uint32_t)BG * W; e += blockDim.x) kmax = max(kmax, cnt[e] & 0xFFFFu);
+            kmax = wave_max(kmax);
+            if (lane == 0) atomicMax(&ctl[2], kmax);
+            __syncthreads();
+            const uint32_t kall = ctl[2];
+            nout = ctl[0];
+            if (ctl[1]) break;                                  // non-finite input
+            fixed_ok = kall < (1u << (10 + h)) && nout <= (uint32_t)kListCap;
+            if (!fixed_ok) {
+                if (nout > (uint32_t)kListCap) {
+                    // no outliers at the columns' true maxima
+                    Elo = binade_exact(colmax[2 * q]);
+                    Ehi = binade_exact(colmax[2 * q + 1]);
+                }
+                while (kall >= (1u << (10 + h))) ++h;
+            }
+            __syncthreads();
+        }
+        if (fixed_ok) {
+            Bfix = fx.B;
+            if (wave == 0 && k == 0) {
+                colS[2 * q] = fx.Slo;
+                colS[2 * q + 1] = fx.Shi;
+            }
+        } else {
             zero_lds(false);
             __syncthreads();
-            run(0, false, fp);
+            run(0, false, fx);
         }
     } else {
         zero_lds(false);
         __syncthreads();
-        run(0, false, fp);
+        run(0, false, fx);
     }
     __syncthreads();
+
+    // The unit's exact fixed-point sum of entry (lb, o, c), rounded once to FP32.
+    auto decode = [&](uint32_t lb, uint32_t o, uint32_t c) -> float {
+        const uint32_t wi = lds_row_fixed<BG>(lb, o, W) + c;
+        const uint32_t cv = cnt[lb * W + o];
+        const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)Bfix - (int64_t)(cv >> 16);
+        const int S = colS[c];
+        const int64_t hi = (int64_t)((const uint32_t*)lds)[wi] - kb;
+        if constexpr (ACC == 2) {
+            const int64_t lo = (int64_t)((const uint32_t*)lds)[nw + wi] - kb;
+            return (float)ldexp((double)(hi * 2097152 + lo), -(S + 21));
+        } else {
+            return ldexpf((float)hi, -S);
+        }
+    };
+    if (fixed_ok && nout > 0) {
+        // Decode the partial to FP32 in place (array 0), then add the outliers.
+        // (each entry is read and rewritten by one thread: no other entry shares its words)
+        const uint32_t total = (uint32_t)BG * W * kNT;
+        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+            const uint32_t c = e % kNT, o = (e / kNT) % W, lb = e / (kNT * W);
+            const float v = decode(lb, o, c);
+            lds[lds_row_fixed<BG>(lb, o, W) + c] = v;
+        }
+        __syncthreads();
+        for (uint32_t r = threadIdx.x; r < nout; r += blockDim.x)
+            __hip_atomic_fetch_add(lds + aux[2 * r], __uint_as_float(aux[2 * r + 1]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+    }
+    // Entry (lb, o, c) of the finished partial.
+    auto entry = [&](uint32_t lb, uint32_t o, uint32_t c) -> float {
+        if (fixed_ok) {
+            if (nout == 0) return decode(lb, o, c);
+            return lds[lds_row_fixed<BG>(lb, o, W) + c];
+        }
+        return lds[lds_row<BG>(lb, o, W) + c];
+    };
 
     // ---- flush the partial into SA -----------------------------------------
     const int64_t r0g = p.row_offset + r_begin;             // first global row of the unit
@@ -556,18 +748,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             const uint32_t c = e % kNT, o = (e / kNT) % W, lb = e / (kNT * W);
             const int cc = c0 + (int)c;
             if (cc >= p.n) continue;
-            float v;
-            if (ACC == 2 && fixed_ok) {
-                // exact unit sum sum(q_hi) * 2^21 + sum(q_lo), rounded once to FP32
-                const uint32_t wi = lds_row_fixed<BG>(lb, o, W) + c;
-                const uint32_t cv = cnt[lb * W + o];
-                const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)fp.B - (int64_t)(cv >> 16);
-                const int64_t hi = (int64_t)((const uint32_t*)lds)[wi] - kb;
-                const int64_t lo = (int64_t)((const uint32_t*)lds)[nw + wi] - kb;
-                v = (float)ldexp((double)(hi * 2097152 + lo), -(fp.S + 21));
-            } else {
-                v = lds[lds_row<BG>(lb, o, W) + c];
-            }
+            const float v = entry(lb, o, c);
             const int64_t b = (int64_t)(j0 + lb) * W + o;
             unsafeAtomicAdd(SA + b * p.ldsa + cc, v * p.scale);
         }
@@ -581,19 +762,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             const int cc = c0 + 2 * (int)cp;
             if (cc >= p.n) continue;
             const int64_t b = (int64_t)(j0 + lb) * W + o;
-            float v0, v1;
-            if (fixed_ok) {
-                // exact sums of the unit, rounded once to FP32
-                const uint32_t* wrd = (const uint32_t*)lds + lds_row_fixed<BG>(lb, o, W) + 2 * cp;
-                const uint32_t cv = cnt[lb * W + o];
-                const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)fp.B - (int64_t)(cv >> 16);
-                v0 = ldexpf((float)((int64_t)wrd[0] - kb), -fp.S);
-                v1 = ldexpf((float)((int64_t)wrd[1] - kb), -fp.S);
-            } else {
-                const uint32_t li = lds_row<BG>(lb, o, W) + 2 * cp;
-                v0 = lds[li];
-                v1 = lds[li + 1];
-            }
+            const float v0 = entry(lb, o, 2 * cp), v1 = entry(lb, o, 2 * cp + 1);
             const uint64_t site = (uint64_t)r0g * dn + (uint64_t)b * (uint64_t)p.n + (uint64_t)cc;
             uint32_t u0 = 0, u1 = 0;
             if (p.mode >= 2) {
@@ -852,8 +1021,9 @@ int apply_max_waves(int32_t a_dtype)
 
 size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual)
 {
-    // fixed-point array(s) + per-bucket-row counters + 4 control words
-    const size_t extra = ((size_t)bg * (size_t)W + 4) * 4;
+    // fixed-point array(s) + per-bucket-row counters + control words + the
+    // outlier list (which holds the exponent sample before the pass)
+    const size_t extra = ((size_t)bg * (size_t)W + kCtlWords + kAuxWords) * 4;
     const size_t narr = dual ? 2 : 1;
     switch (bg) {
     case 1: return narr * lds_words<1>((uint32_t)W) * 4 + extra;

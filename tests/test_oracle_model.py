@@ -47,3 +47,106 @@ def test_f16_model_units_accumulate_close_to_fp64():
     for mode in (1, 2, 3):
         got = model.apply_f16_model(A, 64, 4, 1, mode, 0, chunk_rows=2000).astype(np.float64)
         assert np.linalg.norm(got - ref) <= 4e-3 * np.linalg.norm(ref)
+
+
+# ---- the fixed-point work item (per-column exponent, outlier list) ---------
+
+def _item(X, W=16, waves=8, dual=False, seed=0):
+    """One work item (one block) of rows X with a seeded random bucket map."""
+    g = workloads.rng(seed)
+    R = X.shape[0]
+    bk = g.integers(0, W, size=(R, 1))
+    sg = np.where(g.random((R, 1)) < 0.5, -1, 1)
+    return model.work_item_partial(X, bk, sg, W, waves, dual), bk, sg
+
+
+def _exact(X, bk, sg, W):
+    P = np.zeros((W, X.shape[1]))
+    np.add.at(P, bk[:, 0], sg[:, 0:1] * X)
+    return P
+
+
+def test_column_grid_is_set_by_the_sample_and_small_values_round_to_it():
+    # column 0: sample values 3/8 -> E = binade(0.375) + 2 = 0, S = 19: a value
+    # of 2^-21 lies below half the grid 2^-19 and vanishes; 5 * 2^-20 rounds
+    # to 2 * 2^-19 (ties to even); column 1 is all 2^-10 -> E = -8, S = 27.
+    R = 1024
+    X = np.zeros((R, 2))
+    X[:, 0] = 0.375
+    X[700, 0] = 2.0 ** -21
+    X[701, 0] = 5 * 2.0 ** -20
+    X[:, 1] = 2.0 ** -10
+    (P, h, n_out, redone), bk, sg = _item(X)
+    assert h == 0 and n_out == 0 and not redone
+    expect = _exact(X, bk, sg, 16)
+    # the grid value of 5 * 2^-20 is 2.5 * 2^-19 -> 2 * 2^-19: it loses 2^-20
+    loss = np.zeros_like(expect)
+    loss[bk[700, 0], 0] += sg[700, 0] * 2.0 ** -21
+    loss[bk[701, 0], 0] += sg[701, 0] * 2.0 ** -20
+    assert np.array_equal(P.astype(np.float64), (expect - loss).astype(np.float32))
+
+
+def test_outliers_bypass_the_field_and_are_added_in_fp32():
+    # three large values in column 0 (fewer than the sample rank): outliers,
+    # each one record per block; the rest keeps the fine grid
+    R = 2048
+    X = workloads.rng(4).standard_normal((R, 3)) * 1e-3
+    X[[5, 300, 1500], 0] = [100.0, -250.0, 7.0]
+    (P, h, n_out, redone), bk, sg = _item(X, W=64)
+    assert n_out == 3 and not redone
+    exact = _exact(X, bk, sg, 64)
+    small = X.copy()
+    small[[5, 300, 1500], 0] = 0.0
+    ex_small = _exact(small, bk, sg, 64)
+    # tail entries: within the fixed-point grid (2^(E-19) per contribution)
+    big_rows = {bk[5, 0], bk[300, 0], bk[1500, 0]}
+    mask = np.ones_like(exact, dtype=bool)
+    for b in big_rows:
+        mask[b, 0] = False
+    err = np.abs(P.astype(np.float64) - exact)[mask]
+    assert err.max() <= 64 * 2.0 ** -27                   # E = -8 -> grid 2^-27
+    # entries holding an outlier: fl32(fl32(small part) + outlier) per row
+    for i in (5, 300, 1500):
+        b = bk[i, 0]
+        expect = np.float32(np.float32(ex_small[b, 0]) + np.float32(sg[i, 0] * X[i, 0]))
+        if sum(bk[j, 0] == b for j in (5, 300, 1500)) == 1:
+            assert P[b, 0] == expect
+
+
+def test_four_large_values_set_the_exponent_and_overflowing_lists_redo_at_the_maximum():
+    R = 4096
+    X = workloads.rng(5).standard_normal((R, 1)) * 1e-3
+    # four sample lanes (rows 0, 1, 2, 3 are lanes k = 0..3 of wave 0) hold 10:
+    # the 4th largest lane maximum is 10, so nothing is an outlier
+    X[0:4, 0] = 10.0
+    (P, h, n_out, redone), bk, sg = _item(X)
+    assert n_out == 0 and not redone
+    # 1100 values of 10 outside the sample: the list (1024 records) overflows,
+    # the item is redone with E = binade(10) = 3 and keeps every value exact
+    Y = workloads.rng(6).standard_normal((R, 1)) * 1e-3
+    Y[2048:2048 + 1100, 0] = 10.0
+    (P, h, n_out, redone), bk, sg = _item(Y)
+    assert redone and n_out == 0
+    assert np.allclose(P, _exact(Y, bk, sg, 16), rtol=0, atol=4096 * 2.0 ** -16)
+
+
+def test_count_headroom_grows_when_a_bucket_row_takes_many_rows():
+    R = 3000
+    X = np.ones((R, 2))
+    g = workloads.rng(7)
+    bk = np.zeros((R, 1), dtype=np.int64)          # every row in bucket row 0
+    sg = np.where(g.random((R, 1)) < 0.5, -1, 1)
+    P, h, n_out, redone = model.work_item_partial(X, bk, sg, 4, 8, False)
+    assert h == 2 and redone                       # K = 3000 needs K < 2^(10+h)
+    assert P[0, 0] == sg.sum()
+
+
+def test_dual_fields_carry_the_residual():
+    R = 1024
+    X = workloads.rng(8).standard_normal((R, 4)).astype(np.float32).astype(np.float64)
+    (P, h, n_out, redone), bk, sg = _item(X, dual=True)
+    exact = _exact(X, bk, sg, 16)
+    # grid 2^(E - 40) with E <= 4 for N(0,1) samples: far below FP32 rounding
+    assert np.max(np.abs(P - exact) / np.maximum(np.abs(exact), 1.0)) <= 2.0 ** -23
+    (P1, _, _, _), _, _ = _item(X, dual=False)
+    assert np.max(np.abs(P1 - exact)) > np.max(np.abs(P - exact))

@@ -16,6 +16,10 @@ problems, Section 5):
                Section 5.2), spread evenly over the rows.
   integers     uniform integers in [-lim, lim]: inputs whose partial sums are
                exact in FP32, for bit-exact checks.
+  table1       the coherent adversarial least-squares problem of Section 5.3
+               (Table 1): A = [I_n; tau G / sqrt(m - n)], b = [x* + eta;
+               (tau G / sqrt(m - n)) x*] with eta = noise * N(0,1), the rows
+               of A and b permuted together.
 """
 from __future__ import annotations
 
@@ -50,6 +54,23 @@ def integers(m, n, seed, lim=8, dtype=np.float32):
     return rng(seed).integers(-lim, lim + 1, size=(m, n)).astype(dtype)
 
 
+def table1(m, n, seed, dtype=np.float32, tau=1e-3, noise=0.5):
+    """(A, b, x*): the Section 5.3 construction at m x n; A stored in
+    `dtype`, b in FP64 from the FP64 tail (before the cast)."""
+    g = rng(seed)
+    tail = g.standard_normal((m - n, n)) * (tau / np.sqrt(m - n))
+    xs = g.standard_normal(n)
+    eta = noise * g.standard_normal(n)
+    perm = g.permutation(m)
+    A = np.empty((m, n))
+    b = np.empty(m)
+    A[perm[:n]] = np.eye(n)
+    A[perm[n:]] = tail
+    b[perm[:n]] = xs + eta
+    b[perm[n:]] = tail @ xs
+    return A.astype(dtype), b, xs
+
+
 def family(name, m, n, seed, dtype=np.float32):
     if name == "gaussian":
         return gaussian(m, n, seed, dtype)
@@ -59,6 +80,8 @@ def family(name, m, n, seed, dtype=np.float32):
         return spikes(m, n, dtype)
     if name == "integers":
         return integers(m, n, seed, dtype=dtype)
+    if name == "table1":
+        return table1(m, n, seed, dtype)[0]
     raise ValueError(name)
 
 
