@@ -104,7 +104,9 @@ typedef struct sk_schedule {
  *   s        1..16, nonzeros per column (the paper's zeta).
  *   seed     64-bit key of the row hash; S is a pure function of (m, d, s,
  *            seed) and hash version 1, never stored.
- *   rounding SK_ACC_F32 / SK_ACC_F16_RN / SK_ACC_F16_SR / SK_ACC_F16_DITHER.
+ *   rounding SK_ACC_F32 / SK_ACC_F16_RN / SK_ACC_F16_SR / SK_ACC_F16_DITHER,
+ *            or SK_ACC_BF16_RN / SK_ACC_BF16_SR / SK_ACC_BF16_DITHER (BF16
+ *            output, sketch_apply only).
  *   out      receives the handle.
  * Allocates no device memory.  Errors: SK_EINVAL.
  */
@@ -318,7 +320,7 @@ typedef struct sk_solve_info {
     double rel_residual;     /* ||b - A x|| / ||b|| of the returned x         */
     double rel_residual_x0;  /* the same for the sketch-and-solve start x0    */
     double ms_sketch;        /* sketch of A and b                             */
-    double ms_factor;        /* Gram matrix, Cholesky, R^-1, x0               */
+    double ms_factor;        /* Householder QR of [SA | Sb], R^-1, M, x0      */
     double ms_refine;        /* residuals and LSQR                            */
     double ms_total;
     double reserved[4];
@@ -474,6 +476,15 @@ const char *sketch_last_error(void);
 
 /* sketch_version -- library version * 100 + hash version. */
 int sketch_version(void);
+
+/*
+ * sketch_sync -- wait for the work this library enqueued on `stream` (NULL:
+ * the default stream) and report an asynchronous HIP failure of that work,
+ * which the enqueueing calls cannot see.  h may be NULL; a non-NULL h is
+ * only checked for validity.  Returns SK_OK, or SK_EHIP with the HIP message
+ * in sketch_last_error().
+ */
+int sketch_sync(sk_handle h, void *stream);
 
 #ifdef __cplusplus
 }

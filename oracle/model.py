@@ -117,10 +117,10 @@ def binade(v):
     return np.where(v > 0, e.astype(np.int64) - 1, -1000)
 
 
-def default_plan(s):
+def default_plan(s, elem_bytes=2):
     """(block_group, waves) the planner picks when a block group fits in LDS."""
     bg = next(b for b in (8, 4, 2, 1) if s % b == 0)
-    return bg, (16 if bg >= 8 else 8)
+    return bg, (8 if elem_bytes == 4 else 16)
 
 
 def work_item_partial(X, bk, sg, W, waves, dual):
@@ -174,6 +174,8 @@ def work_item_partial(X, bk, sg, W, waves, dual):
             E = binade(absX.max(axis=0) if R else np.zeros(C))
         while kall >= (1 << (10 + h)):
             h += 1
+        if h > 16:
+            raise ValueError("a bucket row with 2**26 rows or more takes the float path; not modelled")
     S = 19 - h - Ec
     scaled = np.where(out, 0.0, X) * np.ldexp(1.0, S)[None, :]
     q = np.rint(scaled)

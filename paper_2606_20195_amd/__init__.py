@@ -17,7 +17,7 @@ from ._lib import (ACC_BF16_DITHER, ACC_BF16_RN, ACC_BF16_SR, ACC_F16_DITHER, AC
                    Problem, Request, Result, Schedule, ServerInfo, SketchError, SolveInfo, SolveOpts, check, load)
 
 __all__ = ["Sketch", "SketchError", "Schedule", "Batch", "Server", "simulate_admission", "tune_batch", "load_tuning", "clear_tuning", "quantize",
-           "qr_f32", "trinv_f32", "version", "ACC_F32",
+           "qr_f32", "trinv_f32", "version", "sync", "ACC_F32",
            "ACC_F16_RN",
            "ACC_F16_SR", "ACC_F16_DITHER", "ACC_BF16_RN", "ACC_BF16_SR", "ACC_BF16_DITHER", "F32", "F16", "BF16",
            "ACCUMULATE"]
@@ -56,6 +56,12 @@ def _matrix(t, name):
 
 def version():
     return load().sketch_version()
+
+
+def sync(stream=None):
+    """Wait for the library's work on `stream` and raise on an asynchronous
+    HIP failure of that work (sketch_sync)."""
+    check(load().sketch_sync(None, _stream(stream)), "sketch_sync")
 
 
 class Sketch:

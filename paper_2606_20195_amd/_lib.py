@@ -26,7 +26,7 @@ EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedu
            "sketch_batch_destroy", "sketch_apply_batched", "sketch_tune_batch", "sketch_tune_apply",
            "sketch_load_tuning", "sketch_clear_tuning", "sk_server_create", "sk_server_footprint",
            "sk_server_submit", "sk_server_poll", "sk_server_wait", "sk_server_stats", "sk_server_clock",
-           "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version")
+           "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version", "sketch_sync")
 
 
 class Schedule(ctypes.Structure):
@@ -152,6 +152,7 @@ def load():
         "sk_server_simulate": ([ctypes.c_size_t, i32, i32, P, P, P, P, P], ctypes.c_int),
         "sketch_last_error": ([], ctypes.c_char_p),
         "sketch_version": ([], ctypes.c_int),
+        "sketch_sync": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

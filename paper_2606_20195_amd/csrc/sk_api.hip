@@ -114,8 +114,9 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
     pl.bgroups = h->s / pl.bg;
     pl.col_tiles = (int32_t)((n + 31) / 32);
     const int maxw = apply_max_waves(a_dtype);
-    // 8 waves measured fastest for up to 4 blocks per workgroup, 16 for 8 blocks
-    const int autow = std::min(maxw, pl.bg >= 8 ? 16 : 8);
+    // the most waves the element type allows (16 for 16-bit A, 8 for FP32 A)
+    // measured fastest: more waves keep more LDS atomics in flight
+    const int autow = maxw;
     pl.waves = (f && f->waves) ? f->waves : autow;
     if (pl.waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", pl.waves, maxw);
     const int64_t per_unit = (int64_t)pl.col_tiles * pl.bgroups;
@@ -127,16 +128,13 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         pl.chunk_rows = f->chunk_rows;
         if (pl.chunk_rows > max_chunk)
             return set_error(SK_EUNSUPPORTED, "chunk_rows = %d spans more than 2 GiB", pl.chunk_rows);
-        if (pl.chunk_rows > kMaxChunkRows)
-            return set_error(SK_EINVAL, "chunk_rows = %d exceeds %d (16-bit per-bucket counts)", pl.chunk_rows,
-                             kMaxChunkRows);
     } else {
         const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)(dev.lds_max / pl.lds_bytes));
         const int64_t target = std::max<int64_t>(1, (int64_t)dev.cus * wg_per_cu / per_unit);
         int64_t chunk = (rows + target - 1) / target;
         chunk = (chunk + 63) / 64 * 64;
         chunk = std::max<int64_t>(chunk, 2048);
-        chunk = std::min<int64_t>(std::min<int64_t>(chunk, max_chunk), kMaxChunkRows);
+        chunk = std::min<int64_t>(chunk, max_chunk);
         pl.chunk_rows = (int32_t)chunk;
     }
     pl.units = rows > 0 ? (rows + pl.chunk_rows - 1) / pl.chunk_rows : 0;
@@ -149,8 +147,8 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
 
 static int check_schedule(const sk_schedule* s)
 {
-    if (s->chunk_rows < 0 || s->chunk_rows % 64 || s->chunk_rows > kMaxChunkRows)
-        return set_error(SK_EINVAL, "chunk_rows must be a multiple of 64 in 0..%d", kMaxChunkRows);
+    if (s->chunk_rows < 0 || s->chunk_rows % 64)
+        return set_error(SK_EINVAL, "chunk_rows must be a non-negative multiple of 64");
     if (s->block_group && s->block_group != 1 && s->block_group != 2 && s->block_group != 4 && s->block_group != 8)
         return set_error(SK_EINVAL, "block_group must be 0, 1, 2, 4 or 8");
     if (s->waves && s->waves != 4 && s->waves != 8 && s->waves != 16)
@@ -176,6 +174,14 @@ int sketch_version(void) { return SK_LIB_VERSION * 100 + SK_HASH_VERSION; }
 
 const char* sketch_last_error(void) { return g_err; }
 
+int sketch_sync(sk_handle, void* stream)
+{
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "asynchronous failure on the stream");
+    return SK_OK;
+}
+
 int sketch_create(int64_t m, int64_t d, int32_t s, uint64_t seed, int32_t rounding, sk_handle* out)
 {
     if (!out) return set_error(SK_EINVAL, "out is NULL");
@@ -200,7 +206,7 @@ int sketch_create(int64_t m, int64_t d, int32_t s, uint64_t seed, int32_t roundi
 int sketch_destroy(sk_handle h)
 {
     if (!h) return SK_OK;
-    if (h->ws) (void)hipFree(h->ws);
+    if (h->ws && !h->ws_borrowed) (void)hipFree(h->ws);
     solve_release(h);
     delete h;
     return SK_OK;
@@ -300,6 +306,8 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     // d x n FP32 workspace held by the handle (allocated on first need)
     auto ensure_ws = [&](size_t need) -> int {
         if (h->ws_floats >= need) return SK_OK;
+        if (h->ws_borrowed)
+            return set_error(SK_EINVAL, "borrowed workspace of %zu floats is smaller than %zu", h->ws_floats, need);
         if (h->ws) (void)hipFree(h->ws);
         h->ws = nullptr;
         h->ws_floats = 0;

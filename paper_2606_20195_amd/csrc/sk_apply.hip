@@ -174,12 +174,11 @@ constexpr int kMaxThreads = sizeof(AT) == 4 ? 512 : 1024;
 // single FMA, y = x * 2^S_c + 2^23 + B, whose low 23 bits are B + q; XOR with
 // 0x4B000000 (sign +) or 0x4B000000 | (2B - 1) (sign -) turns y's bits into
 // the field value, the negative case being B - q - 1.  A per-bucket-row
-// counter holds the number K of contributions (low 16 bits) and of negative
-// ones N (high 16 bits), so the field sum F decodes exactly to
+// counter (64 bits) holds the number K of contributions (low 32 bits) and of
+// negative ones N (high 32 bits), so the field sum F decodes exactly to
 // sum(sigma*q) = F - K*B + N as long as no field exceeds 2^32 (K < 2^(10+h);
 // the count headroom h is 0 unless a bucket row takes 1024 or more
-// contributions in one unit; the planner keeps units below 65536 rows so K
-// and N fit their 16 bits).
+// contributions in one unit; beyond h = 16 the unit takes the float path).
 //
 // E_c comes from a sample, the first 64-row tile of every wave: each lane's
 // largest |x| in the column over its 16 rows of that tile, and
@@ -196,6 +195,7 @@ constexpr uint32_t kMagicBits = 0x4B000000u;   // bit pattern of 2^23
 constexpr int kListCap = 1024;                 // outlier records per work item
 constexpr int kSampleRank = 4;                 // rank of the lane maximum that sets E_c
 constexpr int kHeadroom = 2;                   // binades of E_c above that lane maximum
+constexpr int kMaxHeadroom = 16;               // largest count headroom h (K < 2^26)
 constexpr int kCtlWords = 8 + 2 * kNT;         // control words, per-column S, per-column maximum
 constexpr int kAuxWords = 2 * kListCap;        // the outlier list; before the pass, the sample
 static_assert(kAuxWords >= 16 * 4 * kNT, "the sample of 16 waves must fit the list area");
@@ -374,8 +374,8 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     const uint32_t W = p.W;
     const size_t nw = lds_words<BG>(W);
     const size_t narr = (ACC == 2) ? 2 : 1;       // fixed-point arrays
-    uint32_t* cnt = (uint32_t*)lds + narr * nw;   // per bucket row, K | N << 16
-    uint32_t* ctl = cnt + (size_t)BG * W;         // [0] outliers, [1] non-finite, [2] max K
+    uint64_t* cnt = (uint64_t*)((uint32_t*)lds + narr * nw);   // per bucket row, K | N << 32
+    uint32_t* ctl = (uint32_t*)(cnt + (size_t)BG * W);         // [0] outliers, [1] non-finite, [2] max K
     int* colS = (int*)ctl + 8;                    // per column: E (sample), then S
     uint32_t* colmax = ctl + 8 + kNT;             // per column: largest |x| (FP32 bits)
     uint32_t* aux = ctl + kCtlWords;              // sample, then outlier list
@@ -409,7 +409,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     // control words).
     auto zero_lds = [&](bool with_counters) {
         const size_t base = with_counters ? narr * nw : nw;
-        const size_t words = base + (with_counters ? (size_t)BG * W + kCtlWords : 0);
+        const size_t words = base + (with_counters ? 2 * (size_t)BG * W + kCtlWords : 0);
         float4* l4 = (float4*)lds;
         for (size_t e = threadIdx.x; e < base / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
         for (size_t e = base + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
@@ -443,8 +443,9 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             for (int lb = 0; lb < BG; ++lb) {
                 const uint32_t wi = (j0 & 3u) + (uint32_t)lb;
                 const uint32_t w = (wi < 4u) ? word_of(w4a, wi) : word_of(w4b, wi - 4u);
-                __hip_atomic_fetch_add(&cnt[(uint32_t)lb * W + bucket_in_block(w, W)], 1u + ((w & 1u) << 16),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&cnt[(uint32_t)lb * W + bucket_in_block(w, W)],
+                                       (uint64_t)1u + ((uint64_t)(w & 1u) << 32), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
 #pragma unroll
@@ -665,21 +666,22 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             if (live_hi) atomicMax(&colmax[2 * q + 1], a1);
             uint32_t kmax = 0;
             __syncthreads();
-            for (uint32_t e = threadIdx.x; e < (uint32_t)BG * W; e += blockDim.x) kmax = max(kmax, cnt[e] & 0xFFFFu);
+            for (uint32_t e = threadIdx.x; e < (uint32_t)BG * W; e += blockDim.x) kmax = max(kmax, (uint32_t)cnt[e]);
             kmax = wave_max(kmax);
             if (lane == 0) atomicMax(&ctl[2], kmax);
             __syncthreads();
             const uint32_t kall = ctl[2];
             nout = ctl[0];
             if (ctl[1]) break;                                  // non-finite input
-            fixed_ok = kall < (1u << (10 + h)) && nout <= (uint32_t)kListCap;
+            fixed_ok = (uint64_t)kall < (1ull << (10 + h)) && nout <= (uint32_t)kListCap;
             if (!fixed_ok) {
                 if (nout > (uint32_t)kListCap) {
                     // no outliers at the columns' true maxima
                     Elo = binade_exact(colmax[2 * q]);
                     Ehi = binade_exact(colmax[2 * q + 1]);
                 }
-                while (kall >= (1u << (10 + h))) ++h;
+                while (h <= kMaxHeadroom && (uint64_t)kall >= (1ull << (10 + h))) ++h;
+                if (h > kMaxHeadroom) break;                   // too many rows in one bucket row
             }
             __syncthreads();
         }
@@ -704,8 +706,8 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     // The unit's exact fixed-point sum of entry (lb, o, c), rounded once to FP32.
     auto decode = [&](uint32_t lb, uint32_t o, uint32_t c) -> float {
         const uint32_t wi = lds_row_fixed<BG>(lb, o, W) + c;
-        const uint32_t cv = cnt[lb * W + o];
-        const int64_t kb = (int64_t)(cv & 0xFFFFu) * (int64_t)Bfix - (int64_t)(cv >> 16);
+        const uint64_t cv = cnt[lb * W + o];
+        const int64_t kb = (int64_t)(uint32_t)cv * (int64_t)Bfix - (int64_t)(cv >> 32);
         const int S = colS[c];
         const int64_t hi = (int64_t)((const uint32_t*)lds)[wi] - kb;
         if constexpr (ACC == 2) {
@@ -1023,7 +1025,7 @@ size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual)
 {
     // fixed-point array(s) + per-bucket-row counters + control words + the
     // outlier list (which holds the exponent sample before the pass)
-    const size_t extra = ((size_t)bg * (size_t)W + kCtlWords + kAuxWords) * 4;
+    const size_t extra = (2 * (size_t)bg * (size_t)W + kCtlWords + kAuxWords) * 4;
     const size_t narr = dual ? 2 : 1;
     switch (bg) {
     case 1: return narr * lds_words<1>((uint32_t)W) * 4 + extra;

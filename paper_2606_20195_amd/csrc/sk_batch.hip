@@ -267,8 +267,8 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
     if (!probs || count < 1) return set_error(SK_EINVAL, "empty batch");
     if (count > 65535) return set_error(SK_EUNSUPPORTED, "at most 65535 problems per batch");
     if (sched) {
-        if (sched->chunk_rows < 0 || sched->chunk_rows % 64 || sched->chunk_rows > kMaxChunkRows)
-            return set_error(SK_EINVAL, "chunk_rows must be a multiple of 64 in 0..%d", kMaxChunkRows);
+        if (sched->chunk_rows < 0 || sched->chunk_rows % 64)
+            return set_error(SK_EINVAL, "chunk_rows must be a non-negative multiple of 64");
         if (sched->block_group && sched->block_group != 1 && sched->block_group != 2 && sched->block_group != 4 &&
             sched->block_group != 8)
             return set_error(SK_EINVAL, "block_group must be 0, 1, 2, 4 or 8");

@@ -20,6 +20,7 @@ struct sk_sketch {
     // FP32 workspace for SK_ACCUMULATE when 1/sqrt(s) is not a power of two
     float *ws = nullptr;
     size_t ws_floats = 0;
+    bool ws_borrowed = false;   // ws lies in memory owned elsewhere (a solve job's block)
     // device workspace of sketch_solve (allocated on first use)
     sk::SolveWs *sw = nullptr;
 };
@@ -50,9 +51,6 @@ struct Plan {
 };
 
 size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual);
-// Largest unit (rows) of the LDS-partial kernels: a bucket row's contribution
-// count K and negative count N are 16-bit fields of one LDS word.
-constexpr int32_t kMaxChunkRows = 65472;
 int make_plan(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo &dev,
               Plan *out);
 int apply_max_waves(int32_t a_dtype);

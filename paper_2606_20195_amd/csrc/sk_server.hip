@@ -339,6 +339,11 @@ int start_request(sk_server* srv, Slot& sl, ReqState* q)
 void finish_request(sk_server* srv, Slot& sl, int rc)
 {
     ReqState* q = sl.req;
+    // Kernels still queued on the slot's stream (a failed phase's, or LSQR
+    // launches after convergence, which exit at once) may touch the request's
+    // block: drain the stream before the block goes back to the allocator.
+    (void)hipStreamSynchronize(sl.st);
+    (void)hipGetLastError();
     q->status = rc;
     job_info(sl.job, &q->info);
     if (sl.gen_timed) {

@@ -1510,6 +1510,8 @@ hipError_t launch_rows(int a_dtype, bool resid, const Geo& g, const RowArgs& a, 
 // recorded after the last state copy and, once the device is there, reads
 // the state and enqueues the next phase.  sketch_solve drives one job to the
 // end; the request server keeps one job per slot and interleaves them.
+constexpr size_t kNoWs = ~(size_t)0;
+
 struct SolveJob {
     // problem
     sk_sketch S;                 // the S of A (its large-d/s workspace is the job's own)
@@ -1528,6 +1530,7 @@ struct SolveJob {
     RowArgs ra{};
     size_t oM = 0, o16 = 0, ob32 = 0, ou = 0, oP = 0, oPT = 0, otau = 0, ot = 0, ov = 0, ow = 0, oy = 0, opart = 0,
            ost = 0, otk = 0, oTq = 0, total = 0;
+    size_t ows = kNoWs, owsb = kNoWs;  // sketch workspaces in the block (large d/s), or none
     // device binding
     hipStream_t st = nullptr;
     char* base = nullptr;
@@ -1558,8 +1561,6 @@ void job_delete(SolveJob* j)
     for (hipEvent_t& e : j->ev)
         if (e) (void)hipEventDestroy(e);
     if (j->ev_state) (void)hipEventDestroy(j->ev_state);
-    if (j->Sb.ws) (void)hipFree(j->Sb.ws);
-    if (j->S.ws) (void)hipFree(j->S.ws);       // the job's own (large d/s sketches)
     delete j;
 }
 
@@ -1599,14 +1600,13 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     const int64_t rpw = (m + nwg0 - 1) / nwg0;
     if (rpw * lda * esz >= ((int64_t)1 << 31))
         return set_error(SK_EUNSUPPORTED, "rows per workgroup span more than 2 GiB");
-    float* own_ws = j->S.ws;                    // kept across prepares of this job
-    const size_t own_floats = j->S.ws_floats;
     j->S = S;
-    j->S.ws = own_ws;                            // never the caller's handle workspace
-    j->S.ws_floats = own_floats;
+    j->S.ws = nullptr;                           // never the caller's handle workspace
+    j->S.ws_floats = 0;
+    j->S.ws_borrowed = true;                     // set from the job's block at start
     j->S.sw = nullptr;
-    if (j->Sb.ws) (void)hipFree(j->Sb.ws);
     j->Sb = sk_sketch{};
+    j->Sb.ws_borrowed = true;
     j->Sb.m = S.m;
     j->Sb.d = S.d;
     j->Sb.s = S.s;
@@ -1644,6 +1644,17 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     j->opart = take((size_t)j->nwg * pst * 8);
     j->ost = take(sizeof(SolveState));
     j->otk = take(64);
+    // Sketches whose d/s rows do not fit in LDS sum in a d x n FP32
+    // workspace; it is carved from the job's block so admission by
+    // footprint stays honest and a job never allocates.
+    {
+        DeviceInfo dv = dev;
+        Plan pa, pb;
+        j->ows = (make_plan(&j->S, a_dtype, m, n, lda, dv, &pa) == SK_OK && pa.global) ? take((size_t)d * n * 4)
+                                                                                        : kNoWs;
+        j->owsb = (make_plan(&j->Sb, SK_F32, m, 1, 1, dv, &pb) == SK_OK && pb.global) ? take((size_t)d * 4) : kNoWs;
+        set_error(SK_OK, "");
+    }
     j->total = off;
 
     RowArgs& ra = j->ra;
@@ -1660,15 +1671,7 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     ra.ldp = n;
     ra.pst = pst;
     j->phase = 0;
-    // Sketches whose d/s rows do not fit in LDS sum in a d x n FP32
-    // workspace that sketch_apply allocates beside the job's block; count it
-    // (and b's d x 1 one) so admission by footprint stays honest.
-    size_t extra = 0;
-    Plan pa, pb;
-    if (make_plan(&j->S, a_dtype, m, n, lda, dev, &pa) == SK_OK && pa.global) extra += (size_t)S.d * n * 4;
-    if (make_plan(&j->Sb, SK_F32, m, 1, 1, dev, &pb) == SK_OK && pb.global) extra += (size_t)S.d * 4;
-    set_error(SK_OK, "");
-    *footprint = j->total + extra;
+    *footprint = j->total;
     return SK_OK;
 }
 
@@ -1751,6 +1754,10 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     ra.part = (double*)(base + j->opart);
     ra.st = (SolveState*)(base + j->ost);
     ra.ticket = (uint32_t*)(base + j->otk);
+    j->S.ws = j->ows != kNoWs ? (float*)(base + j->ows) : nullptr;
+    j->S.ws_floats = j->ows != kNoWs ? (size_t)j->S.d * (size_t)j->n : 0;
+    j->Sb.ws = j->owsb != kNoWs ? (float*)(base + j->owsb) : nullptr;
+    j->Sb.ws_floats = j->owsb != kNoWs ? (size_t)j->Sb.d : 0;
     j->k = 0;
     j->launched = 0;
     j->steps = 0;

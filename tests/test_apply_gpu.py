@@ -212,6 +212,45 @@ def test_full_size_apply(dt, mode, tol):
     assert rel_fro(got, ref) <= tol
 
 
+_FULL = {}
+
+
+def _full(kind, dt):
+    """The 4194304 x 64 input of one family, cached for the module."""
+    key = (kind, dt)
+    if key not in _FULL:
+        _FULL.clear()
+        _FULL[key] = workloads.apply_case(kind, dtype=dt)
+    return _FULL[key]
+
+
+@pytest.mark.parametrize("kind,dt,s,mode,tol", [
+    ("gaussian", np.float16, 4, ACC_F16_SR, 4e-3),
+    ("gaussian", np.float16, 4, ACC_F16_DITHER, 4e-3),
+    ("gaussian", np.float16, 1, ACC_F16_RN, 4e-3),
+    ("gaussian", np.float16, 8, ACC_F16_RN, 4e-3),
+    ("gaussian", np.float16, 8, ACC_F16_SR, 4e-3),
+    ("gaussian", np.float32, 4, ACC_F16_RN, 4e-3),
+    ("gaussian", np.float32, 4, ACC_F16_DITHER, 4e-3),
+    ("gaussian", np.float32, 1, ACC_F32, 1e-5),
+    ("gaussian", np.float32, 8, ACC_F32, 1e-5),
+    ("coherent", np.float16, 4, ACC_F32, 1e-5),
+    ("coherent", np.float16, 4, ACC_F16_SR, 4e-3),
+    ("coherent", np.float16, 4, ACC_F16_DITHER, 4e-3),
+    ("spikes", np.float16, 4, ACC_F32, 1e-5),
+    ("spikes", np.float16, 8, ACC_F16_DITHER, 4e-3),
+    ("coherent", np.float32, 4, ACC_F32, 1e-5),
+])
+def test_full_size_cfg2_grid(kind, dt, s, mode, tol):
+    """The headline configuration (4194304 x 64, d = 1024) over input
+    families, storage types, s and accumulation rules, each against the FP64
+    oracle with the same S."""
+    A = _full(kind, dt)
+    got = run(to_dev(A), A.shape[0], 1024, s, 0, mode, epoch=1)
+    ref = native.sketch_f64(A, 1024, s, 0)
+    assert rel_fro(got, ref) <= tol, (kind, dt, s, mode)
+
+
 def test_full_size_coherent_and_spikes_fp16():
     for kind in ("coherent", "spikes"):
         A = workloads.apply_case(kind, dtype=np.float16)
@@ -276,3 +315,15 @@ def test_workspace_path_empty_row_range(rounding):
     sk.apply(A, SA=SA)
     torch.cuda.synchronize()
     assert torch.all(SA == 0)
+
+
+def test_one_bucket_row_per_block_beyond_16_bit_counts():
+    # d = s: every row of a unit lands in the one bucket row of each block, so
+    # a unit of 98304 rows gives K = 98304 contributions per bucket row (the
+    # count headroom grows to 7); integer input keeps every sum exact
+    rows, n, d, s = 100000, 8, 4, 4
+    A = workloads.integers(rows, n, seed=61, lim=3)
+    sk = Sketch(rows, d, s, 5, ACC_F32)
+    sk.set_schedule(chunk_rows=98304)
+    got = sk.apply(to_dev(A)).cpu().numpy()
+    assert np.array_equal(got, model.apply_f32_exact_int(A, d, s, 5))
