@@ -157,6 +157,24 @@ int sketch_apply(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int6
                  uint32_t round_epoch, void *stream);
 
 /*
+ * sketch_apply_noalloc -- sketch_apply for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, semantics and results as
+ * sketch_apply; it calls no hipMalloc or hipFree.  Where sketch_apply would
+ * use the handle's d x n FP32 workspace (d/s beyond the LDS partials, BF16
+ * output, FP32 accumulation into SA with a non-power-of-two 1/sqrt(s)), it
+ * uses instead a static device scratch array of 4194304 floats (16 MiB) that
+ * the library holds on each GPU it runs on until the process ends; it clears
+ * what it uses with a fill kernel.  Calls that would need more than
+ * d * n = 4194304 workspace floats fail with SK_EINVAL.  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (two streams,
+ * two threads) race and give wrong results.
+ */
+int sketch_apply_noalloc(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int64_t n,
+                         int64_t lda, int64_t row_offset, void *SA, int64_t ldsa, uint32_t flags,
+                         uint32_t round_epoch, void *stream);
+
+/*
  * sketch_set_schedule -- force a schedule for later sketch_apply calls on h
  * (NULL restores the automatic choice).  Fields are checked against the
  * handle at apply time.  Errors: SK_EINVAL (bad field values).

@@ -97,8 +97,12 @@ class Sketch:
         torch = _torch()
         return torch.empty((self.d, n), dtype=self.out_dtype, device=device or "cuda")
 
-    def apply(self, A, SA=None, row_offset=0, accumulate=False, epoch=0, stream=None):
-        """SA = S[:, row_offset:row_offset+rows] @ A (or +=, with accumulate)."""
+    def apply(self, A, SA=None, row_offset=0, accumulate=False, epoch=0, stream=None, noalloc=False):
+        """SA = S[:, row_offset:row_offset+rows] @ A (or +=, with accumulate).
+        noalloc: call sketch_apply_noalloc (no device allocation; SA must be
+        given, the library's static scratch takes any workspace)."""
+        if noalloc and SA is None:
+            raise ValueError("noalloc needs SA")
         lda = _matrix(A, "A")
         rows, n = A.shape
         if SA is None:
@@ -106,10 +110,11 @@ class Sketch:
         ldsa = _matrix(SA, "SA")
         if SA.dtype != self.out_dtype or tuple(SA.shape) != (self.d, n):
             raise ValueError("SA must be a (%d, %d) %s tensor" % (self.d, n, self.out_dtype))
-        check(self._lib.sketch_apply(self._h, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), rows, n, lda,
-                                     int(row_offset), ctypes.c_void_p(SA.data_ptr()), ldsa,
-                                     ACCUMULATE if accumulate else 0, int(epoch) & 0xFFFFFFFF,
-                                     _stream(stream)), "sketch_apply")
+        fn = self._lib.sketch_apply_noalloc if noalloc else self._lib.sketch_apply
+        check(fn(self._h, ctypes.c_void_p(A.data_ptr()), _dtype_code(A), rows, n, lda,
+                 int(row_offset), ctypes.c_void_p(SA.data_ptr()), ldsa,
+                 ACCUMULATE if accumulate else 0, int(epoch) & 0xFFFFFFFF,
+                 _stream(stream)), "sketch_apply_noalloc" if noalloc else "sketch_apply")
         return SA
 
     def solve(self, A, b, x=None, tol=0.0, inner_tol=0.0, max_refine=0, max_inner=0, epoch=0, stream=None,

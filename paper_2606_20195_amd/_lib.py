@@ -26,7 +26,8 @@ EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedu
            "sketch_batch_destroy", "sketch_apply_batched", "sketch_tune_batch", "sketch_tune_apply",
            "sketch_load_tuning", "sketch_clear_tuning", "sk_server_create", "sk_server_footprint",
            "sk_server_submit", "sk_server_poll", "sk_server_wait", "sk_server_stats", "sk_server_clock",
-           "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version", "sketch_sync")
+           "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version", "sketch_sync",
+           "sketch_apply_noalloc")
 
 
 class Schedule(ctypes.Structure):
@@ -120,6 +121,7 @@ def load():
         "sketch_create": ([i64, i64, i32, u64, i32, ctypes.POINTER(P)], ctypes.c_int),
         "sketch_destroy": ([P], ctypes.c_int),
         "sketch_apply": ([P, P, i32, i64, i64, i64, i64, P, i64, u32, u32, P], ctypes.c_int),
+        "sketch_apply_noalloc": ([P, P, i32, i64, i64, i64, i64, P, i64, u32, u32, P], ctypes.c_int),
         "sketch_set_schedule": ([P, ctypes.POINTER(Schedule)], ctypes.c_int),
         "sketch_plan": ([P, i32, i64, i64, ctypes.POINTER(Schedule)], ctypes.c_int),
         "sketch_hash": ([P, i64, i64, P, P, P], ctypes.c_int),

@@ -161,6 +161,33 @@ static int check_schedule(const sk_schedule* s)
     return SK_OK;
 }
 
+// Workspace of sketch_apply_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code uses the device address from
+// hipGetSymbolAddress, taken once per device with that device current (the
+// array's name is only a host-side stand-in).  Every call on a GPU shares its
+// copy, so calls that overlap on one GPU race.
+constexpr size_t kNoallocFloats = (size_t)1 << 22;    // 16 MiB: d * n <= 4194304
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+static int scratch_address(float** out)
+{
+    static std::mutex mu;
+    static float* addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return set_error(SK_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        addr[dev] = (float*)p;
+    }
+    *out = addr[dev];
+    return SK_OK;
+}
+
 static float value_scale32(int32_t s) { return (float)(1.0 / std::sqrt((double)s)); }
 static bool scale_is_pow2(int32_t s) { return s == 1 || s == 4 || s == 16; }
 
@@ -246,8 +273,12 @@ int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedu
     return SK_OK;
 }
 
-int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
-                 int64_t row_offset, void* SA, int64_t ldsa, uint32_t flags, uint32_t round_epoch, void* stream)
+// sketch_apply with the d x n FP32 workspace (large d/s, BF16 output, FP32
+// accumulation with a non-power-of-two scale) either held by the handle
+// (ext_ws == nullptr: allocated on first need) or given by the caller.
+static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
+                      int64_t row_offset, void* SA, int64_t ldsa, uint32_t flags, uint32_t round_epoch,
+                      void* stream, float* ext_ws, size_t ext_floats)
 {
     if (!h) return set_error(SK_EINVAL, "handle is NULL");
     const int esz = elem_size(a_dtype);
@@ -304,16 +335,27 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     const float cs = value_scale32(h->s);
 
     // d x n FP32 workspace held by the handle (allocated on first need)
+    float* ws = nullptr;
     auto ensure_ws = [&](size_t need) -> int {
-        if (h->ws_floats >= need) return SK_OK;
-        if (h->ws_borrowed)
-            return set_error(SK_EINVAL, "borrowed workspace of %zu floats is smaller than %zu", h->ws_floats, need);
-        if (h->ws) (void)hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_floats = 0;
-        if ((e = hipMalloc((void**)&h->ws, need * sizeof(float))) != hipSuccess)
-            return set_error(SK_ENOMEM, "workspace of %zu floats: %s", need, hipGetErrorString(e));
-        h->ws_floats = need;
+        if (ext_ws) {
+            if (need > ext_floats)
+                return set_error(SK_EINVAL, "the d x n workspace of %zu floats exceeds the %zu-float scratch", need,
+                                 ext_floats);
+            ws = ext_ws;
+            return SK_OK;
+        }
+        if (h->ws_floats < need) {
+            if (h->ws_borrowed)
+                return set_error(SK_EINVAL, "borrowed workspace of %zu floats is smaller than %zu", h->ws_floats,
+                                 need);
+            if (h->ws) (void)hipFree(h->ws);
+            h->ws = nullptr;
+            h->ws_floats = 0;
+            if ((e = hipMalloc((void**)&h->ws, need * sizeof(float))) != hipSuccess)
+                return set_error(SK_ENOMEM, "workspace of %zu floats: %s", need, hipGetErrorString(e));
+            h->ws_floats = need;
+        }
+        ws = h->ws;
         return SK_OK;
     };
     if (bf16) {
@@ -323,14 +365,14 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
             return SK_OK;
         }
         if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
-        if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
-        a.SA = h->ws;
+        if ((e = launch_fill(ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+        a.SA = ws;
         a.ldsa = n;
         a.mode = 0;
         a.scale = 1.0f;
         e = pl.global ? launch_contrib(a_dtype, a, st) : launch_apply(a_dtype, pl, a, st);
         if (e != hipSuccess) return hip_fail(e, "apply kernel");
-        e = launch_finish_bf16(h->ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
+        e = launch_finish_bf16(ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
                                (uint64_t)row_offset * (uint64_t)h->d * (uint64_t)n, round_epoch, a.k0, a.k1,
                                accumulate, st);
         return e == hipSuccess ? SK_OK : hip_fail(e, "finish kernel");
@@ -344,8 +386,8 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
             return SK_OK;
         }
         if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
-        if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
-        a.SA = h->ws;
+        if ((e = launch_fill(ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+        a.SA = ws;
         a.ldsa = n;
         a.mode = 0;
         a.scale = 1.0f;
@@ -353,10 +395,10 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
         if (f16) {
             if (!accumulate && (e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess)
                 return hip_fail(e, "fill SA");
-            e = launch_finish16(h->ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
+            e = launch_finish16(ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
                                 (uint64_t)row_offset * (uint64_t)h->d * (uint64_t)n, round_epoch, a.k0, a.k1, st);
             if (e != hipSuccess) return hip_fail(e, "finish kernel");
-        } else if ((e = launch_scale((float*)SA, h->d, n, ldsa, h->ws, cs, accumulate ? 1 : 0, st)) != hipSuccess) {
+        } else if ((e = launch_scale((float*)SA, h->d, n, ldsa, ws, cs, accumulate ? 1 : 0, st)) != hipSuccess) {
             return hip_fail(e, "scale kernel");
         }
         return SK_OK;
@@ -408,14 +450,31 @@ int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int6
     // SA += fl32(c_s * sum).
     if (rows == 0) return SK_OK;
     if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
-    if ((e = launch_fill(h->ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
-    a.SA = h->ws;
+    if ((e = launch_fill(ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
+    a.SA = ws;
     a.ldsa = n;
     a.scale = 1.0f;
     if ((e = launch_apply(a_dtype, pl, a, st)) != hipSuccess) return hip_fail(e, "apply kernel");
-    if ((e = launch_scale((float*)SA, h->d, n, ldsa, h->ws, cs, 1, st)) != hipSuccess)
+    if ((e = launch_scale((float*)SA, h->d, n, ldsa, ws, cs, 1, st)) != hipSuccess)
         return hip_fail(e, "scale kernel");
     return SK_OK;
+}
+
+int sketch_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
+                 int64_t row_offset, void* SA, int64_t ldsa, uint32_t flags, uint32_t round_epoch, void* stream)
+{
+    return apply_impl(h, A, a_dtype, rows, n, lda, row_offset, SA, ldsa, flags, round_epoch, stream, nullptr, 0);
+}
+
+int sketch_apply_noalloc(sk_handle h, const void* A, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda,
+                         int64_t row_offset, void* SA, int64_t ldsa, uint32_t flags, uint32_t round_epoch,
+                         void* stream)
+{
+    float* ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return apply_impl(h, A, a_dtype, rows, n, lda, row_offset, SA, ldsa, flags, round_epoch, stream, ws,
+                      kNoallocFloats);
 }
 
 int sketch_hash(sk_handle h, int64_t row_begin, int64_t count, int32_t* buckets, int8_t* signs, void* stream)
