@@ -423,7 +423,8 @@ def ls_rows(A, b, ratios, seed, tag):
             ev = torch.linalg.eigvalsh(X.T @ X)             # sigma^2 of SA, ascending
             kappa = float(torch.sqrt(ev[-1] / ev[0]).item()) if ev[0] > 0 else float("inf")
             del X, ev, SA
-            path = "workspace" if sk.plan(0, m, n)["block_group"] == 0 else "partials"
+            plan = sk.plan(0, m, n)
+            path = "workspace" if plan["block_group"] == 0 else "tiles%d" % plan["col_tile"]
             x, info = sk.solve(A, b, raise_on_notconv=False)
             row = {"problem": tag, "d_over_n": r, "method": name, "sketch_path": path,
                    "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),
@@ -461,7 +462,7 @@ def dense_ls_problem(m, n, noise, offset, seed):
     return A, b
 
 
-def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16), tau=1e-3, noise=0.5, seed=11):
+def ls_paper_leg(m=1 << 21, n=1024, ratios=(2, 4, 8, 16, 24), tau=1e-3, noise=0.5, seed=11):
     """The paper's coherent adversarial least-squares problem (Section 5,
     sketch-and-solve least squares, Table 1): A = [I_n; tau G / sqrt(m-n)],
     b = [x* + eta; (tau G / sqrt(m-n)) x*] with eta = noise * N(0,1), rows

@@ -80,7 +80,14 @@ typedef struct sk_schedule {
     int32_t waves;        /* waves (64 lanes) per workgroup: 4, 8 or 16       */
     int32_t xcd_remap;    /* 1: place all tiles of a unit on one XCD; 0: off  */
     int32_t per_contribution; /* 1: the paper's kernel scheme, see below      */
-    int32_t reserved[3];  /* must be zero                                     */
+    int32_t col_tile;     /* columns per workgroup tile: 32, 8, 4 or 2; with  */
+                          /* 32: block_group 1, 2, 4 or 8; 8: 1, 2 or 4;      */
+                          /* 4: 1 or 2; 2: 1.  Narrow tiles fit larger d/s   */
+                          /* in LDS and waste no lanes when n is small        */
+    int32_t global_atomics; /* 1: no LDS partials: the call's contributions   */
+                          /* go by FP32 global atomics into a d x n workspace */
+                          /* (the path taken when no tile fits in LDS)        */
+    int32_t reserved[1];  /* must be zero                                     */
 } sk_schedule;
 
 /*

@@ -101,8 +101,8 @@ def unit_partials(A, d, s, seed, chunk_rows, row_offset=0):
     return out
 
 
-# Fixed-point accumulation of one work item (unit x 32-column tile x group of
-# block_group SparseStack blocks), as the apply kernel computes it.
+# Fixed-point accumulation of one work item (unit x tile of nt columns x group
+# of block_group SparseStack blocks), as the apply kernel computes it.
 LIST_CAP = 1024        # outlier records per work item
 SAMPLE_RANK = 4        # rank of the lane maximum that sets a column's exponent
 HEADROOM = 2           # binades of the exponent above that lane maximum
@@ -117,13 +117,15 @@ def binade(v):
     return np.where(v > 0, e.astype(np.int64) - 1, -1000)
 
 
-def default_plan(s, elem_bytes=2):
-    """(block_group, waves) the planner picks when a block group fits in LDS."""
-    bg = next(b for b in (8, 4, 2, 1) if s % b == 0)
-    return bg, (8 if elem_bytes == 4 else 16)
+def default_plan(s, elem_bytes=2, n=64):
+    """(block_group, waves, col_tile) the planner picks when a 32-column tile
+    (an 8-column one for n <= 16) with the most blocks fits in LDS."""
+    nt = 8 if n <= 16 else 32
+    bg = next(b for b in ((8, 4, 2, 1) if nt == 32 else (4, 2, 1)) if s % b == 0)
+    return bg, (8 if elem_bytes == 4 else 16), nt
 
 
-def work_item_partial(X, bk, sg, W, waves, dual):
+def work_item_partial(X, bk, sg, W, waves, dual, nt=TILE_COLS):
     """Unscaled FP32 partial of one work item.
 
     X: the unit's rows of the tile's live columns as stored values upcast
@@ -132,9 +134,10 @@ def work_item_partial(X, bk, sg, W, waves, dual):
     blocks; waves: waves per workgroup; dual: the FP32 mode's two fields.
     Returns (P, h, n_out, redone): P is BG*W x C float32 (block-major).
 
-    1. Sample: lane (k, slot) of wave w sees rows 64w + 4g + k, g < 16, of the
-       unit's first 64*waves rows; its largest |x| per column is one sample
-       value, and E_c = binade(4th largest of the 4*waves values) + 2.
+    1. Sample: with L = nt/2 lanes per row slot and K = 64/L slots, the lane
+       of slot k in wave w sees rows 64w + K g + k, g < L, of the unit's first
+       64*waves rows; its largest |x| per column is one sample value, and
+       E_c = binade(4th largest of the K*waves values) + 2.
     2. A contribution with |x| >= 2**(E_c + 1) is an outlier; the others are
        rounded to q = rne(x * 2**S_c), S_c = 19 - h - E_c (E_c clamped to
        [-108 - h, 145 - h]); the FP32 mode adds the residual's
@@ -154,7 +157,9 @@ def work_item_partial(X, bk, sg, W, waves, dual):
     rows = WAVE_ROWS * waves
     Xs = np.zeros((rows, C))
     Xs[:min(R, rows)] = absX[:rows]
-    lane_max = Xs.reshape(waves, 16, 4, C).max(axis=1).reshape(4 * waves, C)
+    L = nt // 2
+    K = 64 // L
+    lane_max = Xs.reshape(waves, L, K, C).max(axis=1).reshape(K * waves, C)
     M = -np.sort(-lane_max, axis=0)[SAMPLE_RANK - 1]
     E = binade(M) + HEADROOM
     kall = max(int(np.bincount(bk[:, j], minlength=W).max()) if R else 0 for j in range(bg))
@@ -200,31 +205,32 @@ def work_item_partial(X, bk, sg, W, waves, dual):
     return P, h, n_out, redone
 
 
-def unit_partial_fixed(A, d, s, seed, r0, waves=None, block_group=None, dual=False):
+def unit_partial_fixed(A, d, s, seed, r0, waves=None, block_group=None, dual=False, col_tile=None):
     """Unscaled FP32 partial (d x n) of one unit of rows A (first global row
     r0), assembled from its work items."""
     from .sketch import hash_rows
     check_shape(d, s)
-    bgd, wd = default_plan(s)
-    bg = block_group or bgd
-    waves = waves or wd
     A = np.asarray(A)
     R, n = A.shape
+    bgd, wd, ntd = default_plan(s, n=n)
+    bg = block_group or bgd
+    waves = waves or wd
+    nt = col_tile or ntd
     W = d // s
     b, g = hash_rows(seed, np.arange(R, dtype=np.uint64) + np.uint64(r0), d, s)
     off = b - (np.arange(s, dtype=np.int64) * W)[None, :]
     X = A.astype(np.float64)
     P = np.zeros((d, n), dtype=np.float32)
     for j0 in range(0, s, bg):
-        for c0 in range(0, n, TILE_COLS):
-            c1 = min(c0 + TILE_COLS, n)
-            Pi, _, _, _ = work_item_partial(X[:, c0:c1], off[:, j0:j0 + bg], g[:, j0:j0 + bg], W, waves, dual)
+        for c0 in range(0, n, nt):
+            c1 = min(c0 + nt, n)
+            Pi, _, _, _ = work_item_partial(X[:, c0:c1], off[:, j0:j0 + bg], g[:, j0:j0 + bg], W, waves, dual, nt)
             P[j0 * W:(j0 + bg) * W, c0:c1] = Pi
     return P
 
 
 def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=None, waves=None,
-                    block_group=None):
+                    block_group=None, col_tile=None):
     """FP16-mode result, units added in order.
 
     Each unit partial is `unit_partial_fixed` (the exact sum when every
@@ -242,7 +248,7 @@ def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=No
             + np.arange(n, dtype=np.uint64)[None, :])
     for a, b in units(A.shape[0], chunk_rows):
         r0 = row_offset + a
-        P = unit_partial_fixed(A[a:b], d, s, seed, r0, waves, block_group)
+        P = unit_partial_fixed(A[a:b], d, s, seed, r0, waves, block_group, col_tile=col_tile)
         v = (cs * P).astype(np.float32)
         u = None
         if mode in (ACC_F16_SR, ACC_F16_DITHER):
@@ -252,11 +258,11 @@ def apply_f16_model(A, d, s, seed, mode, epoch, chunk_rows, row_offset=0, SA0=No
     return acc
 
 
-def apply_f32_one_unit_model(A, d, s, seed, row_offset=0, waves=None, block_group=None):
+def apply_f32_one_unit_model(A, d, s, seed, row_offset=0, waves=None, block_group=None, col_tile=None):
     """FP32-mode result when one unit covers the rows: fl32(c_s32 * P) with P
     the two-field fixed-point partial (c_s32 is applied to the FP32 partial,
     exactly, when it is a power of two, else once to the FP32 total)."""
-    P = unit_partial_fixed(A, d, s, seed, row_offset, waves, block_group, dual=True)
+    P = unit_partial_fixed(A, d, s, seed, row_offset, waves, block_group, dual=True, col_tile=col_tile)
     return (c_s32(s) * P).astype(np.float32)
 
 

@@ -33,11 +33,13 @@ EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedu
 class Schedule(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int32), ("block_group", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("per_contribution", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("per_contribution", ctypes.c_int32), ("col_tile", ctypes.c_int32),
+                ("global_atomics", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return dict(chunk_rows=self.chunk_rows, block_group=self.block_group, waves=self.waves,
-                    xcd_remap=self.xcd_remap, per_contribution=self.per_contribution)
+                    xcd_remap=self.xcd_remap, per_contribution=self.per_contribution, col_tile=self.col_tile,
+                    global_atomics=self.global_atomics)
 
 
 class Problem(ctypes.Structure):

@@ -85,34 +85,50 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         *out = pl;
         return SK_OK;
     }
+    if (f && f->global_atomics) {
+        Plan g;
+        g.global = true;
+        *out = g;
+        return SK_OK;
+    }
     // FP32 partials (two fields per element) for FP32 and BF16 output
     const bool dual = h->rounding == SK_ACC_F32 || h->rounding >= SK_ACC_BF16_RN;
     Plan pl;
-    // blocks per workgroup
-    if (f && f->block_group) {
-        pl.bg = f->block_group;
-        if (h->s % pl.bg) return set_error(SK_EINVAL, "block_group %d does not divide s = %d", pl.bg, h->s);
-        if (apply_lds_bytes(pl.bg, W, dual) > dev.lds_max)
-            return set_error(SK_EUNSUPPORTED, "block_group %d needs %zu B of LDS (device has %zu)", pl.bg,
-                             apply_lds_bytes(pl.bg, W, dual), dev.lds_max);
-    } else {
+    // Column tile and blocks per workgroup: the widest tile with the most
+    // blocks that fits in LDS (8-column tiles first when n <= 16, where a
+    // 32-column tile would leave half its lanes idle), then narrower tiles
+    // for larger d/s.
+    const int32_t want_nt = (f && f->col_tile) ? f->col_tile : 0;
+    const int32_t want_bg = (f && f->block_group) ? f->block_group : 0;
+    if (want_bg && h->s % want_bg) return set_error(SK_EINVAL, "block_group %d does not divide s = %d", want_bg, h->s);
+    const int32_t order_wide[] = {32, 8, 4, 2}, order_narrow[] = {8, 32, 4, 2};
+    const int32_t* order = (n <= 16) ? order_narrow : order_wide;
+    for (int i = 0; i < 4 && !pl.bg; ++i) {
+        const int32_t nt = order[i];
+        if (want_nt && nt != want_nt) continue;
         for (int bg : {8, 4, 2, 1}) {
-            if (h->s % bg == 0 && apply_lds_bytes(bg, W, dual) <= dev.lds_max) {
+            if (want_bg && bg != want_bg) continue;
+            if (h->s % bg || !apply_tile_ok(nt, bg)) continue;
+            if (apply_lds_bytes(bg, W, dual, nt) <= dev.lds_max) {
                 pl.bg = bg;
+                pl.nt = nt;
                 break;
             }
         }
-        if (!pl.bg) {
-            // no block fits in LDS: FP32 workspace path (sketch_apply)
-            Plan g;
-            g.global = true;
-            *out = g;
-            return SK_OK;
-        }
     }
-    pl.lds_bytes = apply_lds_bytes(pl.bg, W, dual);
+    if (!pl.bg) {
+        if (want_nt || want_bg)
+            return set_error(SK_EUNSUPPORTED, "no kernel for col_tile %d, block_group %d fits %lld bucket rows in LDS",
+                             want_nt, want_bg, (long long)W);
+        // no block fits in LDS: FP32 workspace path (sketch_apply)
+        Plan g;
+        g.global = true;
+        *out = g;
+        return SK_OK;
+    }
+    pl.lds_bytes = apply_lds_bytes(pl.bg, W, dual, pl.nt);
     pl.bgroups = h->s / pl.bg;
-    pl.col_tiles = (int32_t)((n + 31) / 32);
+    pl.col_tiles = (int32_t)((n + pl.nt - 1) / pl.nt);
     const int maxw = apply_max_waves(a_dtype);
     // the most waves the element type allows (16 for 16-bit A, 8 for FP32 A)
     // measured fastest: more waves keep more LDS atomics in flight
@@ -156,8 +172,14 @@ static int check_schedule(const sk_schedule* s)
     if (s->xcd_remap != 0 && s->xcd_remap != 1) return set_error(SK_EINVAL, "xcd_remap must be 0 or 1");
     if (s->per_contribution != 0 && s->per_contribution != 1)
         return set_error(SK_EINVAL, "per_contribution must be 0 or 1");
-    for (int i = 0; i < 3; ++i)
-        if (s->reserved[i]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
+    if (s->col_tile && s->col_tile != 32 && s->col_tile != 8 && s->col_tile != 4 && s->col_tile != 2)
+        return set_error(SK_EINVAL, "col_tile must be 0, 32, 8, 4 or 2");
+    if (s->col_tile && s->block_group && !apply_tile_ok(s->col_tile, s->block_group))
+        return set_error(SK_EINVAL, "no kernel for col_tile %d with block_group %d", s->col_tile, s->block_group);
+    if (s->global_atomics != 0 && s->global_atomics != 1) return set_error(SK_EINVAL, "global_atomics must be 0 or 1");
+    if (s->global_atomics && s->per_contribution)
+        return set_error(SK_EINVAL, "global_atomics and per_contribution exclude each other");
+    if (s->reserved[0]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     return SK_OK;
 }
 
@@ -270,6 +292,8 @@ int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedu
     out->waves = pl.waves;
     out->xcd_remap = pl.xcd_remap;
     out->per_contribution = pl.direct ? 1 : 0;
+    out->col_tile = pl.bg ? pl.nt : 0;
+    out->global_atomics = pl.global ? 1 : 0;
     return SK_OK;
 }
 
@@ -328,6 +352,7 @@ static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     a.chunk_rows = pl.chunk_rows;
     a.col_tiles = pl.col_tiles;
     a.bgroups = pl.bgroups;
+    a.nt = pl.nt;
     a.epoch = round_epoch;
     a.xcd_remap = pl.xcd_remap;
     const uintptr_t vec_align = esz == 4 ? 8u : 4u;

@@ -121,6 +121,8 @@ int parse_tuning(const std::string& text, std::vector<std::pair<std::string, Tun
                             else if (f == "block_group") te.sched.block_group = (int32_t)v;
                             else if (f == "waves") te.sched.waves = (int32_t)v;
                             else if (f == "xcd_remap") te.sched.xcd_remap = (int32_t)v;
+                            else if (f == "col_tile") te.sched.col_tile = (int32_t)v;
+                            else if (f == "global_atomics") te.sched.global_atomics = (int32_t)v;
                             else if (f == "ms") te.ms = v;
                         }
                     } while (c.eat(','));
@@ -170,8 +172,9 @@ int save_tuning(const char* path)
     for (auto& kv : table()) {
         const sk_schedule& s = kv.second.sched;
         fprintf(f, "%s\n  {\"key\": \"%s\", \"chunk_rows\": %d, \"block_group\": %d, \"waves\": %d, \"xcd_remap\": %d, "
-                   "\"ms\": %.6f}",
-                first ? "" : ",", kv.first.c_str(), s.chunk_rows, s.block_group, s.waves, s.xcd_remap, kv.second.ms);
+                   "\"col_tile\": %d, \"global_atomics\": %d, \"ms\": %.6f}",
+                first ? "" : ",", kv.first.c_str(), s.chunk_rows, s.block_group, s.waves, s.xcd_remap, s.col_tile,
+                s.global_atomics, kv.second.ms);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -276,8 +279,11 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
             return set_error(SK_EINVAL, "waves must be 0, 4, 8 or 16");
         if (sched->per_contribution)
             return set_error(SK_EUNSUPPORTED, "per-contribution schedules apply to single sketches only");
-        for (int i = 0; i < 3; ++i)
-            if (sched->reserved[i]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
+        if (sched->col_tile && sched->col_tile != 32 && sched->col_tile != 8)
+            return set_error(SK_EINVAL, "batches take col_tile 0 (per problem), 32 or 8");
+        if (sched->global_atomics)
+            return set_error(SK_EUNSUPPORTED, "global-atomic schedules apply to single sketches only");
+        if (sched->reserved[0]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     }
     int rc;
     for (int32_t i = 0; i < count; ++i)
@@ -300,14 +306,28 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
     if (sched) use = *sched;
     else (void)tuning_lookup(batch_key(a_dtype, dual, count, bytes, nmax), &use);
 
+    // Column tile per problem: the schedule's, else 8 columns for n <= 16
+    // (a 32-column tile would idle half its lanes or more) and 32 otherwise;
+    // 8-column tiles run with at most 4 blocks per workgroup.
+    auto tile_of = [&](const sk_problem& p, int bgc) {
+        int32_t nt = use.col_tile ? use.col_tile : (p.n <= 16 ? 8 : 32);
+        if (!apply_tile_ok(nt, bgc)) nt = 32;
+        return nt;
+    };
+    auto lds_for = [&](int bgc) {
+        size_t mx = 0;
+        for (int32_t i = 0; i < count; ++i)
+            mx = std::max(mx, apply_lds_bytes(bgc, probs[i].d / probs[i].s, dual, tile_of(probs[i], bgc)));
+        return mx;
+    };
     int bg = use.block_group;
     if (bg) {
         for (int32_t i = 0; i < count; ++i)
             if (probs[i].s % bg) return set_error(SK_EINVAL, "block_group %d does not divide s of problem %d", bg, i);
-        if (apply_lds_bytes(bg, maxW, dual) > dev.lds_max) return set_error(SK_EUNSUPPORTED, "block_group too large");
+        if (lds_for(bg) > dev.lds_max) return set_error(SK_EUNSUPPORTED, "block_group too large");
     } else {
         for (int cand : {8, 4, 2, 1}) {
-            bool ok = apply_lds_bytes(cand, maxW, dual) <= dev.lds_max;
+            bool ok = lds_for(cand) <= dev.lds_max;
             for (int32_t i = 0; ok && i < count; ++i) ok = probs[i].s % cand == 0;
             if (ok) {
                 bg = cand;
@@ -347,7 +367,8 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
         a.k0 = (uint32_t)p.seed;
         a.k1 = (uint32_t)(p.seed >> 32);
         a.chunk_rows = (int32_t)std::min<int64_t>(chunk, max_chunk);
-        a.col_tiles = (int32_t)((p.n + 31) / 32);
+        a.nt = tile_of(p, bg);
+        a.col_tiles = (int32_t)((p.n + a.nt - 1) / a.nt);
         a.bgroups = p.s / bg;
         a.mode = dual ? 0 : p.rounding;
         a.epoch = p.round_epoch;
@@ -378,7 +399,7 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
         sorted[k].a.aligned = vec ? 1 : 0;
     }
     if (total >= 0x7FFFFFFF) return set_error(SK_EUNSUPPORTED, "batch has too many work items");
-    const size_t lds = apply_lds_bytes(bg, maxW, dual);
+    const size_t lds = lds_for(bg);
     const int64_t by_lds = std::max<int64_t>(1, (int64_t)(dev.lds_max / lds));
     const int64_t by_waves = std::max<int64_t>(1, 32 / waves);
     const int64_t grid = std::min<int64_t>(total, (int64_t)dev.cus * std::min(by_lds, by_waves));
@@ -399,6 +420,7 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
     b->sched.block_group = bg;
     b->sched.waves = waves;
     b->sched.xcd_remap = 0;
+    b->sched.col_tile = use.col_tile;
 
     const size_t dbytes = (size_t)count * sizeof(BatchDesc);
     const size_t cnt_off = (dbytes + 255) / 256 * 256;
@@ -557,12 +579,15 @@ int sketch_tune_batch(const sk_problem* probs, int32_t count, const char* cache_
         bytes += (double)probs[i].m * (double)probs[i].n * esize(a_dtype);
         nmax = std::max<int64_t>(nmax, probs[i].n);
     }
-    for (int32_t chunk : {2048, 4096, 8192, 16384}) {
-        for (int32_t waves : {4, 8, 16}) {
+    for (int32_t cand = 0; cand < 24; ++cand) {
+        const int32_t tiles[] = {0, 32}, chunks[] = {2048, 4096, 8192, 16384}, wavesv[] = {4, 8, 16};
+        const int32_t col_tile = tiles[cand / 12], chunk = chunks[(cand / 3) % 4], waves = wavesv[cand % 3];
+        {
             if (waves > maxw) continue;
             sk_schedule s{};
             s.chunk_rows = chunk;
             s.waves = waves;
+            s.col_tile = col_tile;
             sk_batch* b = new (std::nothrow) sk_batch;
             if (!b) {
                 rc = set_error(SK_ENOMEM, "out of host memory");
@@ -625,16 +650,25 @@ int sketch_tune_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     sk_schedule best{};
     double best_ms = 1e30;
     int rc = SK_OK;
-    for (int32_t bg : {1, 2, 4, 8}) {
+    // column tile x blocks per workgroup x rows per unit x waves, and the
+    // global-atomic path (LDS partials against atomics per contribution)
+    static const int32_t kTiles[5] = {32, 8, 4, 2, 0};   // 0: the global-atomic path
+    for (int32_t ti = 0; ti < 5; ++ti) {
+        const int32_t nt = kTiles[ti];
+      for (int32_t bg : {1, 2, 4, 8}) {
         if (h->s % bg) continue;
+        if (nt ? !apply_tile_ok(nt, bg) : bg != 1) continue;
         for (int32_t chunk : {0, 2048, 4096, 8192, 16384, 32768}) {
+            if (!nt && chunk) continue;
             for (int32_t waves : {4, 8, 16}) {
-                if (waves > maxw) continue;
+                if (waves > maxw || (!nt && waves != 4)) continue;
                 sk_schedule s{};
-                s.block_group = bg;
+                s.block_group = nt ? bg : 0;
                 s.chunk_rows = chunk;
-                s.waves = waves;
+                s.waves = nt ? waves : 0;
                 s.xcd_remap = 1;
+                s.col_tile = nt;
+                s.global_atomics = nt ? 0 : 1;
                 tmp.sched = s;
                 tmp.forced = true;
                 rc = sketch_apply(&tmp, A, a_dtype, rows, n, lda, 0, SA, ldsa, 0, 0, stream);
@@ -663,6 +697,8 @@ int sketch_tune_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
             if (rc) break;
         }
         if (rc) break;
+      }
+      if (rc) break;
     }
     if (tmp.ws) (void)hipFree(tmp.ws);
     (void)hipEventDestroy(e0);

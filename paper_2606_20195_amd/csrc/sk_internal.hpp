@@ -40,7 +40,8 @@ int device_info(DeviceInfo *out);
 struct Plan {
     int32_t bg = 0;          // blocks per workgroup
     int32_t bgroups = 0;     // s / bg
-    int32_t col_tiles = 0;   // ceil(n / 32)
+    int32_t nt = 32;         // columns per tile: 32, 8, 4 or 2
+    int32_t col_tiles = 0;   // ceil(n / nt)
     int32_t waves = 0;
     int32_t chunk_rows = 0;
     int64_t units = 0;
@@ -50,7 +51,10 @@ struct Plan {
     bool global = false;     // d/s too large for LDS partials: FP32 workspace of the whole call
 };
 
-size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual);
+// LDS bytes of one work item: bg blocks of W bucket rows of nt columns.
+size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual, int32_t nt);
+// Whether kernels exist for this (column tile, block group).
+bool apply_tile_ok(int32_t nt, int32_t bg);
 int make_plan(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo &dev,
               Plan *out);
 int apply_max_waves(int32_t a_dtype);
@@ -64,6 +68,7 @@ struct ApplyArgs {
     uint32_t W;
     uint32_t k0, k1;
     int32_t chunk_rows, col_tiles, bgroups;
+    int32_t nt;          // columns per tile (the batched kernel dispatches on it)
     int32_t mode;        // 0: FP32 atomics, 1 RN, 2 SR, 3 dither
     float scale;         // multiplier of each flushed partial
     uint32_t epoch;
@@ -80,6 +85,16 @@ struct BatchDesc {
 };
 
 hipError_t launch_apply(int a_dtype, const Plan &plan, const ApplyArgs &args, hipStream_t st);
+// Per element type (sk_apply_f32.hip, sk_apply_f16.hip, sk_apply_bf16.hip).
+hipError_t launch_apply_f32(const Plan &plan, const ApplyArgs &a, hipStream_t st);
+hipError_t launch_apply_f16(const Plan &plan, const ApplyArgs &a, hipStream_t st);
+hipError_t launch_apply_bf16(const Plan &plan, const ApplyArgs &a, hipStream_t st);
+hipError_t batched_f32(int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count, int64_t total_items,
+                       uint32_t *counter, int grid, int waves, size_t lds_bytes, hipStream_t st);
+hipError_t batched_f16(int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count, int64_t total_items,
+                       uint32_t *counter, int grid, int waves, size_t lds_bytes, hipStream_t st);
+hipError_t batched_bf16(int bg, bool vec, bool dual, const BatchDesc *descs, int32_t count, int64_t total_items,
+                        uint32_t *counter, int grid, int waves, size_t lds_bytes, hipStream_t st);
 // One global atomic per contribution (args.mode: 0 FP32 SA, 1..3 FP16 SA).
 hipError_t launch_contrib(int a_dtype, const ApplyArgs &args, hipStream_t st);
 // SA (BF16, ld ldsa) = (or += with one BF16 RN add) the BF16 rounding of fl32(scale * ws).

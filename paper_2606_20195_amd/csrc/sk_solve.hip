@@ -39,7 +39,8 @@ constexpr int kUT = 256;           // threads of the QR trailing update
 constexpr int kTI = 256;           // threads of the triangular inverse (one column per wave)
 constexpr int kCB = 8;             // columns per trailing-update workgroup (maximum)
 constexpr int kMaxN = 1024;
-constexpr int64_t kMaxD = 16384;
+constexpr int64_t kQRRows = 16384;   // rows of one QR factorisation (LDS panel kernel)
+constexpr int64_t kMaxD = 131072;    // sketch rows of sketch_solve (taller sketches: two-level QR)
 
 // Device-resident state of the refinement and of the running LSQR.
 struct SolveState {
@@ -1302,6 +1303,18 @@ __global__ __launch_bounds__(kT) void x0_kernel(const float* PT, int64_t ldp, in
     for (int j = threadIdx.x; j < n; j += kT) x[j] = out[j];
 }
 
+// dst[0:n, 0:n+1] = the upper triangle of src's first n columns (zeros below
+// the diagonal) beside src's column n, for rows 0..n-1.
+__global__ void copy_upper_kernel(const float* src, int64_t lds_, float* dst, int64_t ldd, int32_t n)
+{
+    const int64_t total = (int64_t)n * (n + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / (n + 1);
+        const int c = (int)(i - r * (n + 1));
+        dst[r * ldd + c] = (c < n && c < r) ? 0.0f : src[r * lds_ + c];
+    }
+}
+
 __global__ void cast_f64_f32_kernel(const double* in, float* out, int64_t count)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
@@ -1531,10 +1544,14 @@ struct SolveJob {
     size_t oM = 0, o16 = 0, ob32 = 0, ou = 0, oP = 0, oPT = 0, otau = 0, ot = 0, ov = 0, ow = 0, oy = 0, opart = 0,
            ost = 0, otk = 0, oTq = 0, total = 0;
     size_t ows = kNoWs, owsb = kNoWs;  // sketch workspaces in the block (large d/s), or none
+    int32_t qr_blocks = 1;              // row blocks of a two-level QR (d above kQRRows)
+    int64_t qr_rows = 0;                // rows per block
+    size_t oZ = 0;                      // the stacked triangles [R_1 c_1; ...; R_B c_B]
     // device binding
     hipStream_t st = nullptr;
     char* base = nullptr;
     float* Mw = nullptr;
+    float* Z = nullptr;
     uint16_t* SA16 = nullptr;
     float* b32 = nullptr;
     float* tau = nullptr;
@@ -1637,6 +1654,16 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     j->oPT = take((size_t)n * n * 4);
     j->otau = take((size_t)n * 4 + 4);
     j->oTq = take(32 * 32 * 4);
+    // Sketches taller than one QR: factor row blocks of at most kQRRows rows,
+    // stack their triangles (with the transformed Sb) and factor the stack.
+    j->qr_blocks = (int32_t)((d + kQRRows - 1) / kQRRows);
+    j->qr_rows = (d + j->qr_blocks - 1) / j->qr_blocks;
+    if (j->qr_blocks > 1) {
+        if (j->qr_rows < n + 1 || (int64_t)j->qr_blocks * n > kQRRows)
+            return set_error(SK_EUNSUPPORTED, "d = %lld with n = %lld: the stacked triangles exceed %lld rows",
+                             (long long)d, (long long)n, (long long)kQRRows);
+        j->oZ = take((size_t)j->qr_blocks * n * (n + 1) * 4);
+    }
     j->ot = take((size_t)n * 4);
     j->ov = take((size_t)n * 8);
     j->ow = take((size_t)n * 8);
@@ -1743,6 +1770,7 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     j->b32 = (float*)(base + j->ob32);
     j->tau = (float*)(base + j->otau);
     j->Tq = (float*)(base + j->oTq);
+    j->Z = j->qr_blocks > 1 ? (float*)(base + j->oZ) : nullptr;
     RowArgs& ra = j->ra;
     ra.u = (float*)(base + j->ou);
     ra.t = (float*)(base + j->ot);
@@ -1792,7 +1820,26 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     if ((e = job_record(j, 1)) != hipSuccess) return job_fail(j, hip_err(e, "hipEventRecord"));
 
     // ---- factor: QR of [SA | Sb], P = R^-1, x0 = P Q^T Sb
-    if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, j->Tq, st)) != hipSuccess) return job_fail(j, hip_err(e, "QR kernels"));
+    if (j->qr_blocks == 1) {
+        if ((e = run_qr(j->Mw, d, n + 1, j->ldm, n, j->tau, j->Tq, st)) != hipSuccess)
+            return job_fail(j, hip_err(e, "QR kernels"));
+    } else {
+        // two-level QR: [R c] of the stacked blocks' [R_i c_i] equals that of [SA | Sb]
+        const int64_t ldz = n + 1;
+        for (int32_t i = 0; i < j->qr_blocks; ++i) {
+            const int64_t r0 = (int64_t)i * j->qr_rows, rows = std::min<int64_t>(j->qr_rows, d - r0);
+            if ((e = run_qr(j->Mw + r0 * j->ldm, rows, n + 1, j->ldm, n, j->tau, j->Tq, st)) != hipSuccess)
+                return job_fail(j, hip_err(e, "QR kernels"));
+            hipLaunchKernelGGL(copy_upper_kernel, dim3(256), dim3(256), 0, st, (const float*)(j->Mw + r0 * j->ldm),
+                               j->ldm, j->Z + (int64_t)i * n * ldz, ldz, (int32_t)n);
+            if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "stack kernel"));
+        }
+        if ((e = run_qr(j->Z, (int64_t)j->qr_blocks * n, n + 1, ldz, n, j->tau, j->Tq, st)) != hipSuccess)
+            return job_fail(j, hip_err(e, "QR kernels"));
+        hipLaunchKernelGGL(copy_upper_kernel, dim3(256), dim3(256), 0, st, (const float*)j->Z, ldz, j->Mw, j->ldm,
+                           (int32_t)n);
+        if ((e = hipGetLastError()) != hipSuccess) return job_fail(j, hip_err(e, "stack kernel"));
+    }
     if ((e = run_trinv(j->Mw, j->ldm, n, (float*)ra.M, (float*)ra.PT, n, &ra.st->bad, &ra.st->rfro2, st)) != hipSuccess)
         return job_fail(j, hip_err(e, "inverse kernel"));
     hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 15) / 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st,
@@ -1926,8 +1973,8 @@ int sketch_qr_f32(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
     if (rows < 1 || cols < 1 || ldm < cols || k < 0 || k > rows || k > cols)
         return set_error(SK_EINVAL, "bad shape rows=%lld cols=%lld ldm=%lld k=%lld", (long long)rows,
                          (long long)cols, (long long)ldm, (long long)k);
-    if (rows > kMaxD || cols > kMaxN + 1)
-        return set_error(SK_EUNSUPPORTED, "rows <= %lld and cols <= %d", (long long)kMaxD, kMaxN + 1);
+    if (rows > kQRRows || cols > kMaxN + 1)
+        return set_error(SK_EUNSUPPORTED, "rows <= %lld and cols <= %d", (long long)kQRRows, kMaxN + 1);
     if (k == 0) return SK_OK;
     // the block reflectors' 32 x 32 factor, allocated in stream order
     hipStream_t st = (hipStream_t)stream;

@@ -95,8 +95,17 @@ def test_schedule_validation(lib):
     assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 3, 0, 1))) == _lib.EINVAL
     assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 32, 1))) == _lib.EINVAL
     bad = S(0, 0, 0, 1)
-    bad.reserved[2] = 1
+    bad.reserved[0] = 1
     assert lib.sketch_set_schedule(h, ctypes.byref(bad)) == _lib.EINVAL
+    # column tiles: 32, 8, 4, 2 only, and only with the block groups that have kernels
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 16))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 8, 0, 1, 0, 8))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 2, 0, 1, 0, 2))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 4, 0, 1, 0, 8))) == 0
+    # the global-atomic path: 0 or 1, not with the per-contribution scheme
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 2))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 1, 0, 1))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 1))) == 0
     assert lib.sketch_set_schedule(h, ctypes.byref(S(4096, 4, 8, 0))) == 0
     assert lib.sketch_set_schedule(h, None) == 0
     lib.sketch_destroy(h)

@@ -29,10 +29,10 @@ def _input(kind, rows, n, dtype):
     return workloads.table1(rows, n, 23, dtype)[0]
 
 
-def _one_unit(A, d, s, mode, seed=9, r0=100, epoch=11):
+def _one_unit(A, d, s, mode, seed=9, r0=100, epoch=11, col_tile=0):
     rows, n = A.shape
     sk = Sketch(rows + r0, d, s, seed, mode)
-    sk.set_schedule(chunk_rows=(rows + 63) // 64 * 64)
+    sk.set_schedule(chunk_rows=(rows + 63) // 64 * 64, col_tile=col_tile)
     plan = sk.plan(F16 if A.dtype == np.float16 else F32, rows, n)
     SA = sk.apply(torch.from_numpy(A).cuda(), row_offset=r0, epoch=epoch)
     torch.cuda.synchronize()
@@ -46,7 +46,7 @@ def test_fp16_one_unit_matches_the_fixed_point_model(kind, mode, s, d):
     A = _input(kind, 8192, 40, np.float16)
     got, plan = _one_unit(A, d, s, mode)
     ref = model.apply_f16_model(A, d, s, 9, mode, 11, chunk_rows=8192, row_offset=100,
-                                waves=plan["waves"], block_group=plan["block_group"])
+                                waves=plan["waves"], block_group=plan["block_group"], col_tile=plan["col_tile"])
     bad = np.flatnonzero(got.view(np.uint16) != ref.view(np.uint16))
     assert bad.size == 0, (bad[:8], got.ravel()[bad[:4]], ref.ravel()[bad[:4]])
 
@@ -58,8 +58,28 @@ def test_fp32_one_unit_matches_the_fixed_point_model(kind, dt, s, d):
     A = _input(kind, 6000, 33, dt)
     got, plan = _one_unit(A, d, s, ACC_F32)
     ref = model.apply_f32_one_unit_model(A, d, s, 9, row_offset=100, waves=plan["waves"],
-                                         block_group=plan["block_group"])
+                                         block_group=plan["block_group"], col_tile=plan["col_tile"])
     bad = np.flatnonzero(got != ref)
+    assert bad.size == 0, (bad[:8], got.ravel()[bad[:4]], ref.ravel()[bad[:4]])
+
+
+@pytest.mark.parametrize("col_tile", [8, 4, 2])
+@pytest.mark.parametrize("kind", ["gaussian", "coherent", "table1"])
+@pytest.mark.parametrize("mode", [ACC_F16_RN, ACC_F32])
+def test_narrow_column_tiles_match_the_model(col_tile, kind, mode):
+    """Narrow tiles (quad broadcasts of the row hash, more rows per wave
+    instruction) on a 40-column input: the same one-unit bit-exact bar."""
+    A = _input(kind, 4096, 40, np.float16)
+    d, s = 512, 4
+    got, plan = _one_unit(A, d, s, mode, col_tile=col_tile)
+    assert plan["col_tile"] == col_tile
+    kw = dict(waves=plan["waves"], block_group=plan["block_group"], col_tile=col_tile)
+    if mode == ACC_F32:
+        ref = model.apply_f32_one_unit_model(A, d, s, 9, row_offset=100, **kw)
+        bad = np.flatnonzero(got != ref)
+    else:
+        ref = model.apply_f16_model(A, d, s, 9, mode, 11, chunk_rows=4096, row_offset=100, **kw)
+        bad = np.flatnonzero(got.view(np.uint16) != ref.view(np.uint16))
     assert bad.size == 0, (bad[:8], got.ravel()[bad[:4]], ref.ravel()[bad[:4]])
 
 

@@ -260,18 +260,29 @@ def test_full_size_coherent_and_spikes_fp16():
             assert rel_fro(got, ref) <= 4e-3, (kind, s)
 
 
-# ---- d/s beyond the LDS partials: the FP32 workspace path (one unit per call)
+# ---- large d/s: narrow column tiles in LDS, else the FP32 workspace path
 
-def test_large_bucket_count_plans_the_workspace():
-    sk = Sketch(100000, 4096, 1, 3, ACC_F16_RN)
-    assert sk.plan(1, 100000, 64)["block_group"] == 0
-    assert Sketch(100000, 1024, 4, 3, ACC_F16_RN).plan(1, 100000, 64)["block_group"] > 0
+def test_large_bucket_counts_plan_narrow_tiles_then_the_workspace():
+    p = Sketch(100000, 4096, 1, 3, ACC_F16_RN).plan(1, 100000, 64)
+    assert p["block_group"] == 1 and p["col_tile"] in (4, 2) and p["global_atomics"] == 0
+    p = Sketch(100000, 24576, 4, 3, ACC_F32).plan(0, 100000, 1024)          # Table 1 at d/n = 24
+    assert p["block_group"] == 1 and p["col_tile"] == 2
+    p = Sketch(100000, 1 << 17, 1, 3, ACC_F16_RN).plan(1, 100000, 64)       # 131072 bucket rows
+    assert p["block_group"] == 0 and p["global_atomics"] == 1
+    p = Sketch(100000, 1024, 4, 3, ACC_F16_RN).plan(1, 100000, 64)
+    assert p["block_group"] == 4 and p["col_tile"] == 32
+    p = Sketch(100000, 64, 4, 3, ACC_F16_RN).plan(1, 100000, 16)
+    assert p["col_tile"] == 8
 
 
+PATHS = [None, dict(global_atomics=1)]
+
+
+@pytest.mark.parametrize("sched", PATHS, ids=["tiles", "workspace"])
 @pytest.mark.parametrize("d,s,n", [(4096, 1, 32), (16384, 4, 17), (6000, 3, 40)])
-def test_workspace_path_fp32_integer_is_bit_exact(d, s, n):
+def test_large_ds_fp32_integer_is_bit_exact(d, s, n, sched):
     A = workloads.integers(30000, n, seed=51, lim=6)
-    got = run(to_dev(A), 30000, d, s, 12, ACC_F32)
+    got = run(to_dev(A), 30000, d, s, 12, ACC_F32, sched=sched)
     assert np.array_equal(got, model.apply_f32_exact_int(A, d, s, 12))
 
 
@@ -280,6 +291,7 @@ def test_workspace_path_fp16_integer_is_one_unit(rounding):
     d, s, m, n = 8192, 2, 20000, 24
     A = workloads.integers(m, n, seed=52, lim=5).astype(np.float16)
     sk = Sketch(m + 500, d, s, 13, rounding)
+    sk.set_schedule(global_atomics=1)
     SA = torch.zeros((d, n), dtype=torch.float16, device="cuda")
     sk.apply(to_dev(A), SA=SA, row_offset=500, epoch=6)
     torch.cuda.synchronize()
@@ -287,14 +299,17 @@ def test_workspace_path_fp16_integer_is_one_unit(rounding):
     assert np.array_equal(SA.cpu().numpy().view(np.uint16), ref.view(np.uint16))
 
 
-def test_workspace_path_gaussian_tolerances_and_accumulate():
+@pytest.mark.parametrize("sched", PATHS, ids=["tiles", "workspace"])
+def test_large_ds_gaussian_tolerances_and_accumulate(sched):
     d, s, m, n = 16384, 4, 60000, 32
     A = workloads.gaussian(m, n, 53, np.float16)
     ref = apply_f64(A, d, s, 14)
-    got16 = run(to_dev(A), m, d, s, 14, ACC_F16_SR, epoch=2)
+    got16 = run(to_dev(A), m, d, s, 14, ACC_F16_SR, epoch=2, sched=sched)
     assert rel_fro(got16, ref) <= 4e-3
     # two row shards accumulated equal one call in FP32 mode, to FP32 rounding
     sk = Sketch(m, d, s, 14, ACC_F32)
+    if sched:
+        sk.set_schedule(**sched)
     Ad = to_dev(A)
     SA = sk.apply(Ad[:25000])
     sk.apply(Ad[25000:], SA=SA, row_offset=25000, accumulate=True)
@@ -305,6 +320,7 @@ def test_workspace_path_gaussian_tolerances_and_accumulate():
 @pytest.mark.parametrize("rounding", [ACC_F32, ACC_F16_RN])
 def test_workspace_path_empty_row_range(rounding):
     sk = Sketch(1000, 4096, 1, 2, rounding)
+    sk.set_schedule(global_atomics=1)
     assert sk.plan(1, 1000, 8)["block_group"] == 0
     dt = torch.float32 if rounding == ACC_F32 else torch.float16
     SA = torch.full((4096, 8), 3.0, dtype=dt, device="cuda")

@@ -153,3 +153,23 @@ def test_tuners_write_and_reload_their_choice(tmp_path):
     clear_tuning()
     assert load_tuning(path) >= 2
     clear_tuning()
+
+
+@pytest.mark.parametrize("rounding", [ACC_F16_RN, ACC_F16_DITHER])
+def test_batched_real_valued_one_unit_matches_the_model(rounding):
+    """Gaussian and coherent (outlier) problems, one unit each: every
+    problem's FP16 result equals the oracle's fixed-point model with the
+    batch's schedule (8-column tiles for n <= 16, 32 otherwise)."""
+    shapes = [(3000, 8, 32, 4), (4000, 16, 64, 4), (2500, 40, 160, 4), (3500, 12, 48, 4), (1500, 64, 256, 4)]
+    specs, hosts = _specs(shapes, rounding, np.float16, seed0=300)
+    b = Batch(specs, chunk_rows=4096)
+    b.apply()
+    torch.cuda.synchronize()
+    sch = b.schedule()
+    for sp, A in zip(specs, hosts):
+        nt = 8 if A.shape[1] <= 16 else 32
+        got = sp["SA"].cpu().numpy().view(np.uint16)
+        ref = model.apply_f16_model(A, sp["d"], sp["s"], sp["seed"], rounding, sp["epoch"], chunk_rows=4096,
+                                    waves=sch["waves"], block_group=sch["block_group"], col_tile=nt)
+        bad = np.flatnonzero(got != ref.view(np.uint16))
+        assert bad.size == 0, (A.shape, bad[:8])

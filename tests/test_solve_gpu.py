@@ -243,13 +243,42 @@ def test_solve_full_size_coherent_fp16():
     assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
 
 
-def test_solve_with_a_workspace_sketch():
-    # d/s = 2400 bucket rows: the sketch takes the FP32 workspace path
+@pytest.mark.parametrize("global_atomics", [0, 1])
+def test_solve_with_a_large_ds_sketch(global_atomics):
+    # d/s = 2400 bucket rows: 8-column tiles in LDS, or (forced) the FP32
+    # workspace path, whose workspace lies in the solve's own block
     m, n, d = 60000, 300, 2400
     A = workloads.gaussian(m, n, 71, np.float16)
     b = A.astype(np.float64) @ workloads.rng(72).standard_normal(n) + 1e-6 * workloads.rng(73).standard_normal(m)
     sk = Sketch(m, d, 1, 5, ACC_F16_RN)
-    assert sk.plan(1, m, n)["block_group"] == 0
+    if global_atomics:
+        sk.set_schedule(global_atomics=1)
+        assert sk.plan(1, m, n)["block_group"] == 0
+    else:
+        assert sk.plan(1, m, n)["col_tile"] == 8
     x, info = sk.solve(torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda())
     assert info["converged"] == 1
     assert ne_criterion(A, b, x.cpu().numpy()) <= 1.5e-10
+
+
+@pytest.mark.parametrize("d", [20000, 40000])
+def test_solve_with_a_sketch_taller_than_one_qr(d):
+    # d above 16384 rows: the factor runs a QR per row block, stacks the
+    # blocks' triangles (with their part of Q^T S b) and factors the stack
+    m, n = 120000, 48
+    A = workloads.coherent(m, n, 74, np.float32)
+    b = A.astype(np.float64) @ workloads.rng(75).standard_normal(n) + 1e-6 * workloads.rng(76).standard_normal(m)
+    sk = Sketch(m, d, 4, 6, ACC_F32)
+    x, info = sk.solve(torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda())
+    assert info["converged"] == 1
+    assert ne_criterion(A, b, x.cpu().numpy()) <= 1.5e-10
+    from oracle import native
+    from oracle.sketch import apply_f64
+    x_opt = native.lstsq(A, b)
+    assert np.linalg.norm(x.cpu().numpy() - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
+    # the sketch-and-solve start is the FP64 sketched problem's solution, to
+    # the FP32 QR's rounding (kappa(SA) ~ 1 here: ||A dx|| / ||b|| ~ 2^-24)
+    SAb = apply_f64(np.column_stack([A.astype(np.float64), b]), d, 4, 6)
+    x0 = np.linalg.lstsq(SAb[:, :-1], SAb[:, -1], rcond=None)[0]
+    res0 = np.linalg.norm(A.astype(np.float64) @ x0 - b) / np.linalg.norm(b)
+    assert abs(info["rel_residual_x0"] - res0) <= 1e-3 * res0 + 64 * 2.0 ** -24

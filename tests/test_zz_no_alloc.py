@@ -16,8 +16,10 @@ from paper_2606_20195_amd import ACC_BF16_SR, ACC_F16_DITHER, ACC_F32, SketchErr
 pytestmark = pytest.mark.gpu
 
 
-def _pair(m, d, s, rounding, A, epoch=3, accumulate=False, sa0=None):
+def _pair(m, d, s, rounding, A, epoch=3, accumulate=False, sa0=None, sched=None):
     sk = Sketch(m, d, s, 17, rounding)
+    if sched:
+        sk.set_schedule(**sched)
     dev = torch.from_numpy(A).cuda()
     n = A.shape[1]
     ref = sk.empty_output(n) if sa0 is None else sa0.clone()
@@ -28,15 +30,18 @@ def _pair(m, d, s, rounding, A, epoch=3, accumulate=False, sa0=None):
     return got.cpu(), ref.cpu()
 
 
-@pytest.mark.parametrize("rounding,d,s", [
-    (ACC_F32, 4096, 1),            # d/s beyond the LDS partials: workspace of the whole call
-    (ACC_F16_DITHER, 8192, 2),     # the same with one FP16 rounding per entry
-    (ACC_BF16_SR, 256, 4),         # BF16 output: FP32 sum of the call, then one rounding
+GLOBAL = dict(global_atomics=1)
+
+
+@pytest.mark.parametrize("rounding,d,s,sched", [
+    (ACC_F32, 4096, 1, GLOBAL),           # the global-atomic path: workspace of the whole call
+    (ACC_F16_DITHER, 8192, 2, GLOBAL),    # the same with one FP16 rounding per entry
+    (ACC_BF16_SR, 256, 4, None),          # BF16 output: FP32 sum of the call, then one rounding
 ])
-def test_noalloc_matches_apply_on_two_calls(rounding, d, s):
+def test_noalloc_matches_apply_on_two_calls(rounding, d, s, sched):
     for rows, n in ((30000, 48), (9000, 20)):          # second call smaller
         A = workloads.integers(rows, n, seed=rows + n, lim=4).astype(np.float32)
-        got, ref = _pair(rows, d, s, rounding, A)
+        got, ref = _pair(rows, d, s, rounding, A, sched=sched)
         assert torch.equal(got.view(torch.int16) if got.dtype != torch.float32 else got,
                            ref.view(torch.int16) if ref.dtype != torch.float32 else ref)
 
@@ -52,6 +57,7 @@ def test_noalloc_accumulate_with_a_non_power_of_two_scale():
 
 def test_noalloc_rejects_workspaces_beyond_the_scratch():
     sk = Sketch(1000, 1 << 18, 1, 0, ACC_F32)            # d x n = 2^18 * 32 floats > 2^22
+    sk.set_schedule(global_atomics=1)
     A = torch.zeros((1000, 32), device="cuda")
     SA = torch.zeros((1 << 18, 32), device="cuda")
     with pytest.raises(SketchError, match="scratch"):
