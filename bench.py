@@ -60,10 +60,14 @@ def parse():
                    help="run only the coherence sweep (eta against mu(U)) and print its JSON line")
     p.add_argument("--no-paper-scheme", action="store_true",
                    help="skip timing the one-atomic-per-contribution scheme against the partial-sum kernels")
+    p.add_argument("--leg", default="all", choices=("all", "headline", "batch", "ls", "serve"),
+                   help="run one leg only (for per-leg kernel traces); 'all' is the full benchmark")
+    p.add_argument("--families", action="store_true",
+                   help="run only the per-family report at the headline size (error and eta against FP64)")
     return p.parse_args()
 
 
-APPLY_SOURCES = ("sk_apply.hip", "sk_device.hpp", "sk_internal.hpp")
+APPLY_SOURCES = ("sk_apply_item.hpp", "sk_apply_f16.hip", "sk_device.hpp", "sk_internal.hpp")
 
 
 def kernel_source_digest():
@@ -89,10 +93,16 @@ def measured_traffic():
     return float(val.group(1))
 
 
-def time_calls(fn, steps, stream):
+def time_calls(fn, steps, stream, evict=None):
+    """Per-call times (HIP events on `stream`); with `evict` (a callable), a
+    read of a buffer four times the 256 MB last-level cache runs before each
+    call, outside its events, so the call finds none of its input cached (a
+    read leaves clean lines: no write-back lands in the timed call)."""
     import torch
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for a, b in ev:
+        if evict is not None:
+            evict()
         a.record(stream)
         fn()
         b.record(stream)
@@ -100,26 +110,65 @@ def time_calls(fn, steps, stream):
     return [a.elapsed_time(b) for a, b in ev]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline():
-    """The FP64 C oracle on a bounded sample of the same workload."""
+    """The FP64 C oracle on a bounded sample of the same workload, on all host
+    threads and on one."""
     import workloads
     from oracle import native
     rows = 1 << 20
     A = workloads.gaussian(rows, N, 0, np.float16)
     threads = native.max_threads()
     native.sketch_f64(A[:4096], D, S, 0)                  # load / warm
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        native.sketch_f64(A, D, S, 0, nthreads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 50:
-            break
-    gbs = reps * (A.nbytes + D * N * 2) / el / 1e9
+
+    def rate(nthreads, sample, budget):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            native.sketch_f64(sample, D, S, 0, nthreads=nthreads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > budget or reps >= 50:
+                break
+        return reps * (sample.nbytes + D * N * 2) / el / 1e9, reps
+
+    gbs, reps = rate(threads, A, 10.0)
+    one, reps1 = rate(1, A[:rows // 4], 6.0)
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "first %d rows of the 4194304x64 FP16 input, %d passes, FP64 scatter with OpenMP "
-                      "per-thread partials" % (rows, reps)}
+                      "per-thread partials" % (rows, reps),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_core": {"value": round(one, 3), "unit": "GB/s", "cores": 1,
+                         "sample": "first %d rows, %d passes" % (rows // 4, reps1)}}
+
+
+def ls_oracle_time(A16, b, rows=1 << 17):
+    """The FP64 Householder least-squares oracle (C, OpenMP) and LAPACK
+    (numpy.linalg.lstsq) on the first `rows` rows of the least-squares input,
+    and the oracle's time scaled to all rows (Householder QR is linear in m)."""
+    from oracle import native
+    A = np.ascontiguousarray(A16[:rows])
+    bb = np.ascontiguousarray(b[:rows])
+    t0 = time.perf_counter()
+    native.lstsq(A, bb)
+    t_orc = time.perf_counter() - t0
+    A64 = A.astype(np.float64)
+    t0 = time.perf_counter()
+    np.linalg.lstsq(A64, bb, rcond=None)
+    t_lapack = time.perf_counter() - t0
+    scale = A16.shape[0] / rows
+    return {"sample_rows": rows, "oracle_s": round(t_orc, 3), "oracle_cores": native.max_threads(),
+            "lapack_s": round(t_lapack, 3), "oracle_full_size_s_scaled": round(t_orc * scale, 2),
+            "lapack_full_size_s_scaled": round(t_lapack * scale, 2), "cpu_model": cpu_model()}
 
 
 def ls_leg(nsolves, stream):
@@ -134,10 +183,19 @@ def ls_leg(nsolves, stream):
     bd = torch.from_numpy(b).cuda()
     out = {"workload": "least squares A %dx%d coherent (1e-3 N(0,1), rows 0..%d = 100 I), d=%d, s=4, "
                        "b = A x* + 1e-6 N(0,1); stop at ||A^T r||/(||A||_F ||r||) <= 1e-10" % (m, n, n - 1, d)}
+    # the optimum for the error report: FP64 normal equations of the stored A
+    # (its columns are 100 e_k plus a 1e-3 tail, so kappa(A) ~ 1 and the
+    # normal equations lose nothing)
+    A64 = A16.astype(np.float64)
+    x_opt = np.linalg.solve(A64.T @ A64, A64.T @ b)
+    del A64
     for name, rounding, dt in (("fp16", ACC_F16_RN, torch.float16), ("fp32_plain", ACC_F32, torch.float32)):
         Ad = torch.from_numpy(A16).cuda().to(dt)
         sk = Sketch(m, d, 4, 0, rounding)
         x, info = sk.solve(Ad, bd, epoch=0)           # warm-up: workspace, code objects
+        SAk = sk.apply(Ad).double().cpu().numpy()
+        sv = np.linalg.svd(SAk, compute_uv=False)
+        kappa = float(sv[0] / sv[-1])
         times, infos = [], []
         for k in range(nsolves):
             t0 = time.perf_counter()
@@ -158,11 +216,49 @@ def ls_leg(nsolves, stream):
             "ms_sketch": round(float(np.mean([i["ms_sketch"] for i in infos])), 3),
             "ms_factor": round(float(np.mean([i["ms_factor"] for i in infos])), 3),
             "ms_refine": round(float(np.mean([i["ms_refine"] for i in infos])), 3),
+            "x_err_vs_opt": float(np.linalg.norm(x.cpu().numpy() - x_opt) / np.linalg.norm(x_opt)),
+            "kappa_SA": round(kappa, 4),
         }
         del Ad, sk
         torch.cuda.empty_cache()
     out["fp16_speedup"] = round(out["fp16"]["solves_per_s"] / out["fp32_plain"]["solves_per_s"], 3)
-    return out
+    return out, (A16, b)
+
+
+def families_leg():
+    """Per input family at the headline size (4194304 x 64, d = 1024, s = 4):
+    the relative Frobenius error of SA against the FP64 oracle in every
+    accumulation mode (A stored FP16), and the subspace distortion eta of an
+    orthonormal basis U of the stored A (FP64 Householder QR on the host,
+    stored FP32), from the GPU's sketch and from the oracle's with the same S."""
+    import torch
+    import workloads
+    from oracle import native
+    from oracle.sketch import coherence, distortion
+    from paper_2606_20195_amd import ACC_F16_DITHER, ACC_F16_RN, ACC_F16_SR, ACC_F32, Sketch
+    out = {}
+    modes = (("f32", ACC_F32), ("f16_rn", ACC_F16_RN), ("f16_sr", ACC_F16_SR), ("f16_dither", ACC_F16_DITHER))
+    for kind in ("gaussian", "coherent", "spikes"):
+        A = workloads.apply_case(kind, dtype=np.float16)
+        ref = native.sketch_f64(A, D, S, 0)
+        Ad = torch.from_numpy(A).cuda()
+        row = {}
+        for name, code in modes:
+            got = Sketch(M, D, S, 0, code).apply(Ad, epoch=1).double().cpu().numpy()
+            row["err_" + name] = float("%.4g" % (np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        del Ad
+        U = np.linalg.qr(A.astype(np.float64))[0].astype(np.float32)
+        row["mu_U"] = round(float(coherence(U.astype(np.float64))), 2)
+        row["eta_fp64"] = round(distortion(native.sketch_f64(U, D, S, 0)), 5)
+        Ud = torch.from_numpy(U).cuda()
+        for name, code in modes:
+            got = Sketch(M, D, S, 0, code).apply(Ud, epoch=1).double().cpu().numpy()
+            row["eta_" + name] = round(distortion(got), 5)
+        del Ud, U, A
+        torch.cuda.empty_cache()
+        out[kind] = row
+    return {"workload": "A 4194304x64 stored FP16 per family, d=1024, s=4, sketch seed 0; U = orth(A) stored FP32",
+            "families": out}
 
 
 def batch_leg(reps=10):
@@ -541,11 +637,28 @@ def main():
     if args.coherence:
         print(json.dumps({"coherence_sweep": coherence_leg()}), flush=True)
         return
+    if args.families:
+        print(json.dumps({"families": families_leg()}), flush=True)
+        return
+    if args.leg == "batch":
+        print(json.dumps({"batch": batch_leg()}), flush=True)
+        return
+    if args.leg == "ls":
+        print(json.dumps({"ls": ls_leg(args.ls_solves or 5, torch.cuda.current_stream())[0]}), flush=True)
+        return
+    if args.leg == "serve":
+        print(json.dumps({"serve": serve_leg(args.serve or 500, max(1, (args.serve or 500) // 10))}), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     A = torch.from_numpy(workloads.apply_case("gaussian", dtype=np.float16)).to(dev)
     stream = torch.cuda.current_stream()
     alg_bytes = M * N * 2 + D * N * 2
+    # read between timed kernel calls: 1 GiB, four times the last-level cache
+    from paper_2606_20195_amd import stream_read
+    evict_buf = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    fold = torch.zeros(256, dtype=torch.int32, device=dev)
+    evict = lambda: stream_read(evict_buf, fold)  # noqa: E731
 
     def measure(rounding, steps, warmup, a_tensor):
         sk = Sketch(M, D, S, 0, rounding)
@@ -562,12 +675,19 @@ def main():
         t1.record(stream)
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1) / steps
-        # the apply kernel alone: accumulate calls launch only that kernel
-        per = time_calls(lambda: sk.apply(a_tensor, SA=SA, accumulate=True), steps, stream)
+        # the apply kernel alone (accumulate calls launch only that kernel),
+        # the last-level cache evicted before each call
+        per = time_calls(lambda: sk.apply(a_tensor, SA=SA, accumulate=True), steps, stream, evict)
+        warm = time_calls(lambda: sk.apply(a_tensor, SA=SA, accumulate=True), max(20, steps // 4), stream)
         plan = sk.plan(1 if a_tensor.dtype == torch.float16 else 0, M, N)
-        return ms, float(np.mean(per)), float(np.percentile(per, 99)), plan
+        return ms, float(np.mean(per)), float(np.percentile(per, 99)), plan, float(np.mean(warm))
 
-    ms, kern_ms, kern_p99, plan = measure(ACC_F16_RN, args.steps, args.warmup, A)
+    ms, kern_ms, kern_p99, plan, kern_warm = measure(ACC_F16_RN, args.steps, args.warmup, A)
+    # streaming-read ceiling on the same 512 MiB input (evicted before each read)
+    for _ in range(3):
+        stream_read(A, fold)
+    rd = time_calls(lambda: stream_read(A, fold), 30, stream, evict)
+    read_ceiling = A.numel() * 2 / (float(np.mean(rd)) * 1e-3) / 1e9
     value = alg_bytes / (ms * 1e-3) / 1e9
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
 
@@ -577,24 +697,25 @@ def main():
     for name in [m for m in extra if m in mode_codes]:
         code = mode_codes[name]
         steps = max(20, args.steps // 4)
-        _, kms, _, _ = measure(code, steps, 5, A)
+        _, kms, _, _, _ = measure(code, steps, 5, A)
         out_bytes = D * N * (4 if code == ACC_F32 else 2)
         modes[name] = {"kernel_ms": round(kms, 4), "GB/s": round((M * N * 2 + out_bytes) / (kms * 1e-3) / 1e9, 1)}
     if "a32" in extra:
         # FP32-stored A with FP32 accumulation (the plain path)
         A32 = A.float()
-        _, k32, _, _ = measure(ACC_F32, max(20, args.steps // 4), 5, A32)
+        _, k32, _, _, _ = measure(ACC_F32, max(20, args.steps // 4), 5, A32)
         modes["a_f32_acc_f32"] = {"kernel_ms": round(k32, 4),
                                   "GB/s": round((M * N * 4 + D * N * 4) / (k32 * 1e-3) / 1e9, 1)}
         del A32
 
-    paper = None if args.no_paper_scheme else paper_scheme_leg(A, stream)
-    del A
+    only_headline = args.leg == "headline"
+    paper = None if (args.no_paper_scheme or only_headline) else paper_scheme_leg(A, stream)
+    del A, evict_buf
     torch.cuda.empty_cache()
-    batch = None if args.no_batch else batch_leg()
+    batch = None if (args.no_batch or only_headline) else batch_leg()
     torch.cuda.empty_cache()
-    ls = ls_leg(args.ls_solves, stream) if args.ls_solves > 0 else None
-    serve = serve_leg(args.serve, max(1, args.serve // 10)) if args.serve > 0 else None
+    ls, ls_inputs = ls_leg(args.ls_solves, stream) if (args.ls_solves > 0 and not only_headline) else (None, None)
+    serve = serve_leg(args.serve, max(1, args.serve // 10)) if (args.serve > 0 and not only_headline) else None
     traffic = measured_traffic()
     line = {
         "metric": "sketch_apply HBM GB/s (% of peak) + LS solves/s, p50/p99 at 1e-10 residual, FP16 vs FP32",
@@ -615,8 +736,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "apply_kernel<__half, 4, true>",
+                     "kernel": "apply_kernel<__half, 4, true, 1, 32>",
                      "kernel_ms_mean": round(kern_ms, 5), "kernel_ms_p99": round(kern_p99, 5),
+                     "kernel_timing": "HIP events per call on the launch stream, 1 GiB read between calls "
+                                      "to evict the last-level cache",
+                     "kernel_ms_warm": round(kern_warm, 5),
+                     "read_ceiling_GBs": round(read_ceiling, 1),
+                     "frac_of_read_ceiling": round(achieved / read_ceiling, 4),
                      "algorithmic_bytes": alg_bytes},
         "modes": modes,
     }
@@ -628,8 +754,10 @@ def main():
         line["ls"] = ls
     if serve is not None:
         line["serve"] = serve
-    if not args.no_cpu:
+    if not args.no_cpu and not only_headline:
         line["cpu_baseline"] = cpu_baseline()
+        if ls_inputs is not None:
+            line["ls"]["cpu_oracle"] = ls_oracle_time(*ls_inputs)
     print(json.dumps(line), flush=True)
 
 

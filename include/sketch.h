@@ -511,6 +511,16 @@ int sketch_version(void);
  */
 int sketch_sync(sk_handle h, void *stream);
 
+/*
+ * sketch_stream_read -- measurement export: read `bytes` bytes of device
+ * memory at p once (16-byte non-temporal loads, folded by XOR into out[0..255],
+ * 256 device words the caller provides).  Its time is the streaming-read ceiling of
+ * the device, against which sketch_apply's bandwidth is compared.  bytes: a
+ * positive multiple of 16; p: 16-byte aligned.  Asynchronous on `stream`.
+ * Errors: SK_EINVAL, SK_EHIP.
+ */
+int sketch_stream_read(const void *p, int64_t bytes, uint32_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ from ._lib import (ACC_BF16_DITHER, ACC_BF16_RN, ACC_BF16_SR, ACC_F16_DITHER, AC
                    Problem, Request, Result, Schedule, ServerInfo, SketchError, SolveInfo, SolveOpts, check, load)
 
 __all__ = ["Sketch", "SketchError", "Schedule", "Batch", "Server", "simulate_admission", "tune_batch", "load_tuning", "clear_tuning", "quantize",
-           "qr_f32", "trinv_f32", "version", "sync", "ACC_F32",
+           "qr_f32", "trinv_f32", "version", "sync", "stream_read", "ACC_F32",
            "ACC_F16_RN",
            "ACC_F16_SR", "ACC_F16_DITHER", "ACC_BF16_RN", "ACC_BF16_SR", "ACC_BF16_DITHER", "F32", "F16", "BF16",
            "ACCUMULATE"]
@@ -56,6 +56,14 @@ def _matrix(t, name):
 
 def version():
     return load().sketch_version()
+
+
+def stream_read(t, out, stream=None):
+    """Read every byte of the contiguous device tensor t once (the read
+    ceiling measurement, sketch_stream_read); out: an int32 device tensor of
+    256 elements that receives the XOR folds."""
+    check(load().sketch_stream_read(ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size(),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)), "sketch_stream_read")
 
 
 def sync(stream=None):

@@ -27,7 +27,7 @@ EXPORTS = ("sketch_create", "sketch_destroy", "sketch_apply", "sketch_set_schedu
            "sketch_load_tuning", "sketch_clear_tuning", "sk_server_create", "sk_server_footprint",
            "sk_server_submit", "sk_server_poll", "sk_server_wait", "sk_server_stats", "sk_server_clock",
            "sk_server_destroy", "sk_server_simulate", "sketch_last_error", "sketch_version", "sketch_sync",
-           "sketch_apply_noalloc")
+           "sketch_apply_noalloc", "sketch_stream_read")
 
 
 class Schedule(ctypes.Structure):
@@ -157,6 +157,7 @@ def load():
         "sketch_last_error": ([], ctypes.c_char_p),
         "sketch_version": ([], ctypes.c_int),
         "sketch_sync": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+        "sketch_stream_read": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -223,6 +223,16 @@ int sketch_version(void) { return SK_LIB_VERSION * 100 + SK_HASH_VERSION; }
 
 const char* sketch_last_error(void) { return g_err; }
 
+int sketch_stream_read(const void* p, int64_t bytes, uint32_t* out, void* stream)
+{
+    if (!p || !out) return set_error(SK_EINVAL, "NULL argument");
+    if (bytes < 16 || bytes % 16 || ((uintptr_t)p & 15u))
+        return set_error(SK_EINVAL, "bytes must be a positive multiple of 16 and p 16-byte aligned");
+    (void)hipGetLastError();
+    const hipError_t e = launch_stream_read(p, bytes, out, (hipStream_t)stream);
+    return e == hipSuccess ? SK_OK : hip_fail(e, "stream read kernel");
+}
+
 int sketch_sync(sk_handle, void* stream)
 {
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);

@@ -94,6 +94,29 @@ __global__ void quantize_kernel(int mode, const float* x, uint16_t* out, int64_t
     }
 }
 
+// Streaming read of `bytes` bytes (a multiple of 16): every 16-byte word is
+// loaded once with a non-temporal load and folded by XOR; each wave XORs its
+// fold into one of 256 output words (workgroup id mod 256), so no word takes
+// more than a few dozen atomics.  The read ceiling against which the apply
+// kernel's bandwidth is judged.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_read_kernel(const u32x4* p, int64_t words, uint32_t* out)
+{
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < words; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(p + i), b = __builtin_nontemporal_load(p + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(p + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(p + i + 3 * stride);
+        acc ^= a ^ b ^ c ^ d;
+    }
+    for (; i < words; i += stride) acc ^= __builtin_nontemporal_load(p + i);
+    uint32_t v = acc.x ^ acc.y ^ acc.z ^ acc.w;
+    for (int o = 32; o > 0; o >>= 1) v ^= (uint32_t)__shfl_xor((int)v, o);
+    if ((threadIdx.x & 63) == 0) atomicXor(out + (blockIdx.x & 255u), v);
+}
+
 unsigned grid_for(int64_t work, int threads)
 {
     int64_t g = (work + threads - 1) / threads;
@@ -170,6 +193,12 @@ hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchD
     }
     if (e != hipSuccess || !post_scale) return e;
     hipLaunchKernelGGL(batch_scale_kernel, dim3(fx, (unsigned)count), dim3(256), 0, st, descs, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_read(const void* p, int64_t bytes, uint32_t* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(stream_read_kernel, dim3(8192), dim3(256), 0, st, (const u32x4*)p, bytes / 16, out);
     return hipGetLastError();
 }
 

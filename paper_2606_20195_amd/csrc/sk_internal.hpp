@@ -109,6 +109,7 @@ hipError_t launch_batched(int a_dtype, int bg, bool vec, bool dual, const BatchD
                           int64_t total_items, uint32_t *counter, int grid, int waves, size_t lds_bytes,
                           bool post_scale, int64_t max_dn, hipStream_t st);
 hipError_t launch_fill(void *p, int elem_bytes, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+hipError_t launch_stream_read(const void *p, int64_t bytes, uint32_t *out, hipStream_t st);
 hipError_t launch_scale(float *SA, int64_t d, int64_t n, int64_t ldsa, const float *ws, float c,
                         int accumulate, hipStream_t st);
 hipError_t launch_hash(uint64_t seed, int64_t d, int32_t s, int64_t row_begin, int64_t count,
