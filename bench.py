@@ -524,6 +524,7 @@ def ls_rows(A, b, ratios, seed, tag):
             x, info = sk.solve(A, b, raise_on_notconv=False)
             row = {"problem": tag, "d_over_n": r, "method": name, "sketch_path": path,
                    "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),
+                   "sketch_ms": round(info["ms_sketch"], 3), "factor_ms": round(info["ms_factor"], 3),
                    "rel_res_sketch_and_solve": float("%.4g" % info["rel_residual_x0"]),
                    "kappa_SA": float("%.4g" % kappa),
                    "rel_res_refined": float("%.4g" % info["rel_residual"]),

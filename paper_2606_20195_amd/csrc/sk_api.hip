@@ -59,7 +59,6 @@ static int elem_size(int32_t dt)
     return dt == SK_F32 ? 4 : (dt == SK_F16 || dt == SK_BF16) ? 2 : 0;
 }
 
-int apply_max_waves(int32_t a_dtype);
 
 int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo& dev,
               Plan* out)
@@ -129,11 +128,13 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
     pl.lds_bytes = apply_lds_bytes(pl.bg, W, dual, pl.nt);
     pl.bgroups = h->s / pl.bg;
     pl.col_tiles = (int32_t)((n + pl.nt - 1) / pl.nt);
-    const int maxw = apply_max_waves(a_dtype);
+    const int maxw = apply_max_waves(a_dtype, pl.bg);
     // the most waves the element type allows (16 for 16-bit A, 8 for FP32 A)
     // measured fastest: more waves keep more LDS atomics in flight
     const int autow = maxw;
     pl.waves = (f && f->waves) ? f->waves : autow;
+    // odd n or lda take the scalar-load kernels, built for at most 8 waves
+    if (((n | lda) & 1) && pl.waves > 8) pl.waves = 8;
     if (pl.waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", pl.waves, maxw);
     const int64_t per_unit = (int64_t)pl.col_tiles * pl.bgroups;
     const int esz = elem_size(a_dtype);
@@ -367,6 +368,8 @@ static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     a.xcd_remap = pl.xcd_remap;
     const uintptr_t vec_align = esz == 4 ? 8u : 4u;
     a.aligned = (n % 2 == 0) && (lda % 2 == 0) && ((uintptr_t)A % vec_align == 0);
+    // a base address off the vector alignment also takes the scalar-load kernels
+    if (!a.aligned && pl.waves > 8) pl.waves = 8;
     const float cs = value_scale32(h->s);
 
     // d x n FP32 workspace held by the handle (allocated on first need)

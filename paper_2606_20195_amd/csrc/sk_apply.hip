@@ -127,10 +127,13 @@ unsigned grid_for(int64_t work, int threads)
 
 }  // namespace
 
-int apply_max_waves(int32_t a_dtype)
+int apply_max_waves(int32_t a_dtype, int32_t bg)
 {
+    if (bg >= 8) return 8;
     return (a_dtype == SK_F32 ? kMaxThreads<float> : kMaxThreads<__half>) / 64;
 }
+
+int batch_max_waves() { return kBatchThreads / 64; }
 
 bool apply_tile_ok(int32_t nt, int32_t bg)
 {

@@ -187,6 +187,16 @@ __device__ __forceinline__ void static_for(F&& f)
 // built for 8 waves per workgroup (the same bytes in flight as 16 FP16 waves).
 template <typename AT>
 constexpr int kMaxThreads = sizeof(AT) == 4 ? 512 : 1024;
+// Single-call kernels: eight blocks per workgroup, or the two scalar loads per
+// column pair of unaligned input, need more than the 128 registers a
+// 1024-thread workgroup leaves each lane, so they run at most 8 waves.
+template <typename AT, int BG, bool VEC>
+constexpr int kApplyThreads = (BG >= 8 || !VEC) ? 512 : kMaxThreads<AT>;
+// The persistent kernel keeps the 128-register budget of 1024 threads: its
+// work items are small, and several workgroups per CU (more waves in flight)
+// measured faster than 8 waves with 256 registers (4.33 against 3.60 ms for
+// 512 sketches), even though the two inlined work items spill a few values.
+constexpr int kBatchThreads = 1024;
 
 // Fixed-point LDS partials.
 //
@@ -824,7 +834,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
 }
 
 template <typename AT, int BG, bool VEC, int ACC, int NT>
-__global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
+__global__ __launch_bounds__((kApplyThreads<AT, BG, VEC>)) void apply_kernel(ApplyArgs p)
 {
     extern __shared__ float lds[];
     const int per_unit = p.col_tiles * p.bgroups;
@@ -847,7 +857,7 @@ __global__ __launch_bounds__(kMaxThreads<AT>) void apply_kernel(ApplyArgs p)
 // largest problems' items come first; item0 is a problem's first flat item.
 // A problem's column tile is 32 or 8 columns (a.nt).
 template <typename AT, int BG, bool VEC, int ACC>
-__global__ __launch_bounds__(kMaxThreads<AT>) void apply_batched_kernel(const BatchDesc* descs, int32_t count,
+__global__ __launch_bounds__(kBatchThreads) void apply_batched_kernel(const BatchDesc* descs, int32_t count,
                                                                          int64_t total_items, uint32_t* counter)
 {
     extern __shared__ float lds[];

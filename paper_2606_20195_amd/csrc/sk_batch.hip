@@ -336,8 +336,8 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
         }
         if (!bg) return set_error(SK_EUNSUPPORTED, "d/s = %lld does not fit in LDS", (long long)maxW);
     }
-    const int maxw = apply_max_waves(a_dtype);
-    int waves = use.waves ? use.waves : std::min(maxw, 8);
+    const int maxw = batch_max_waves();
+    int waves = use.waves ? use.waves : 8;
     if (waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", waves, maxw);
     const int32_t chunk = use.chunk_rows ? use.chunk_rows : 4096;
     const int esz = esize(a_dtype);
@@ -561,7 +561,7 @@ int sketch_tune_batch(const sk_problem* probs, int32_t count, const char* cache_
     }
     const int32_t a_dtype = probs[0].a_dtype;
     const bool dual = probs[0].rounding == SK_ACC_F32;
-    const int maxw = apply_max_waves(a_dtype);
+    const int maxw = batch_max_waves();
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
@@ -637,7 +637,7 @@ int sketch_tune_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
 {
     if (!h) return set_error(SK_EINVAL, "handle is NULL");
     if (rows < 1) return set_error(SK_EINVAL, "tuning needs rows >= 1");
-    const int maxw = apply_max_waves(a_dtype);
+    const int maxw = apply_max_waves(a_dtype, 1);
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
@@ -662,6 +662,7 @@ int sketch_tune_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
             if (!nt && chunk) continue;
             for (int32_t waves : {4, 8, 16}) {
                 if (waves > maxw || (!nt && waves != 4)) continue;
+                if (nt && waves > apply_max_waves(a_dtype, bg)) continue;
                 sk_schedule s{};
                 s.block_group = nt ? bg : 0;
                 s.chunk_rows = chunk;

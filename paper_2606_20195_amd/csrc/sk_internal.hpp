@@ -57,7 +57,10 @@ size_t apply_lds_bytes(int32_t bg, int64_t W, bool dual, int32_t nt);
 bool apply_tile_ok(int32_t nt, int32_t bg);
 int make_plan(const sk_sketch *h, int32_t a_dtype, int64_t rows, int64_t n, int64_t lda, const DeviceInfo &dev,
               Plan *out);
-int apply_max_waves(int32_t a_dtype);
+// Most waves per workgroup of the single-call kernels (by element type and
+// blocks per workgroup) and of the persistent batched kernel.
+int apply_max_waves(int32_t a_dtype, int32_t bg);
+int batch_max_waves();
 
 struct ApplyArgs {
     const void *A;
