@@ -407,6 +407,20 @@ __device__ __forceinline__ void zero_halves(PairRaw<AT>& r, bool lo, bool hi)
 // residual at 2^-21 finer resolution, kept in two LDS arrays with the same
 // layout, so each unit is summed with about 41 significant bits below
 // 2^(E_c+1).
+// Maximum of v over the wave, in every lane: DPP shifts within each row of 16
+// lanes (lanes shifted in from outside the row read 0, the identity), then
+// row broadcasts carry the row maxima up to lane 63.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // One work item: the partial sketch of unit `unit` (rows [unit * chunk_rows,
 // ...)), column tile `ct` and block group `bgi`, accumulated in LDS and added
 // into SA.  Called by every thread of the workgroup; ends with LDS free.
@@ -416,7 +430,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     typedef typename MagOf<AT>::type Mag;
     constexpr int LL = Geom<NT>::L, KK = Geom<NT>::K, GG = Geom<NT>::G;
     const int nwaves = (int)(blockDim.x >> 6);
-    const int wave = (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform: tile arithmetic stays scalar
     const int lane = (int)(threadIdx.x & 63);
     const int64_t r_begin = (int64_t)unit * p.chunk_rows;
     const int64_t r_end = min(r_begin + (int64_t)p.chunk_rows, p.rows);
@@ -459,11 +473,11 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     // Clears the partial (and, with the fixed-point arrays, the counters and
     // control words).
     auto zero_lds = [&](bool with_counters) {
-        const size_t base = with_counters ? narr * nw : nw;
-        const size_t words = base + (with_counters ? 2 * (size_t)BG * W + kCtlWords : 0);
+        const uint32_t base = (uint32_t)(with_counters ? narr * nw : nw);
+        const uint32_t words = base + (with_counters ? 2u * (uint32_t)BG * W + (uint32_t)kCtlWords : 0u);
         float4* l4 = (float4*)lds;
-        for (size_t e = threadIdx.x; e < base / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (size_t e = base + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
+        for (uint32_t e = threadIdx.x; e < base / 4; e += blockDim.x) l4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (uint32_t e = base + threadIdx.x; e < words; e += blockDim.x) lds[e] = 0.f;
     };
 
     auto load_tile = [&](PairRaw<AT> (&buf)[GG], int64_t tile) {
@@ -626,60 +640,63 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         return mag;
     };
 
-    // Stream the unit once; `acc` selects the accumulation.  bufA holds the
-    // wave's first tile on entry when `preloaded`.  Returns the lane's column
-    // maxima.
+    // Stream the unit once; `acc` selects the accumulation.  bufA and bufB
+    // hold the wave's first two tiles on entry when `preloaded`.  Returns the
+    // lane's column maxima.
     auto run = [&](int acc, bool preloaded, const Fixed<AT>& fx) {
         const bool fixed = acc != 0;
         Mag mag{};
         int64_t tile = wave;
         if (tile < ntiles) {
-            if (!preloaded) load_tile(bufA, tile);
+            if (!preloaded) {
+                load_tile(bufA, tile);
+                load_tile(bufB, min(tile + nwaves, ntiles));   // tile ntiles lies wholly past the unit
+            }
             hash_tile(offA, sgnA, tile, fixed, fx.xneg);
         }
         // Software pipeline: the next tile's loads are in flight while the
         // current tile is scattered; unrolled twice to ping-pong the buffers.
-        // Rows past the unit's end load as zero and add nothing.  The next
-        // tile is loaded unconditionally (past the last tile every row is out
-        // of the buffer's range and reads zero without touching memory): a
-        // load behind a branch would make the compiler wait for it before
-        // the current tile's values could be used.
+        // Rows past the unit's end load as zero and add nothing.  The tile
+        // after next is loaded unconditionally (past the last tile every row
+        // is out of the buffer's range and reads zero without touching
+        // memory): a load behind a branch would make the compiler wait for it
+        // before the next tile's values could be used.
         while (tile < ntiles) {
             int64_t nxt = tile + nwaves;
-            load_tile(bufB, min(nxt, ntiles));     // tile ntiles lies wholly past the unit
             mag = process(acc, bufA, offA, sgnA, fx, mag);
             if (nxt >= ntiles) break;
+            load_tile(bufA, min(nxt + nwaves, ntiles));
             hash_tile(offB, sgnB, nxt, fixed, fx.xneg);
             tile = nxt;
             nxt = tile + nwaves;
-            load_tile(bufA, min(nxt, ntiles));
             mag = process(acc, bufB, offB, sgnB, fx, mag);
             if (nxt >= ntiles) break;
+            load_tile(bufB, min(nxt + nwaves, ntiles));
             hash_tile(offA, sgnA, nxt, fixed, fx.xneg);
             tile = nxt;
         }
         return mag;
     };
 
-    auto wave_max = [&](uint32_t v) {
-        for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-        return v;
-    };
+    auto wave_max = [&](uint32_t v) { return wave_max_u32(v); };
 
     bool fixed_ok = false;
     uint32_t nout = 0;            // outlier records to add before the flush
     uint32_t Bfix = 0;
     Fixed<AT> fx = fixed_params<AT>(0, 0, 0);
     if constexpr (ACC != 0) {
-        zero_lds(true);
         // The sample: every lane's column maxima over its rows of the wave's
         // first tile, column-major with Ls = K * nwaves values per column.
+        // The wave's second tile is requested with the first, so the memory
+        // stays busy while the exponents are chosen.
         const int Ls = KK * nwaves;
         Mag m0{};
         if (wave < ntiles) {
             load_tile(bufA, wave);
-            m0 = tile_mag(bufA);
+            load_tile(bufB, min((int64_t)wave + nwaves, ntiles));
         }
+        zero_lds(true);
+        if (wave < ntiles) m0 = tile_mag(bufA);
         {
             uint32_t a0, a1;
             mag_cols<AT>(m0, a0, a1);
@@ -687,11 +704,15 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
             aux[(2 * q + 1) * Ls + wave * KK + k] = a1;
         }
         __syncthreads();
-        if (threadIdx.x < (unsigned)NT) {
-            // the kSampleRank-th largest lane maximum of the column (a sorting network step per value)
+        // The kSampleRank-th largest lane maximum of each column (with
+        // multiplicity): wave w takes columns w, w + nwaves, ...; each lane
+        // keeps the largest kSampleRank values of its share in order, then
+        // kSampleRank rounds each take the wave's maximum and drop one
+        // instance of it (from the lowest lane holding it).
+        for (int c = wave; c < NT; c += nwaves) {
             uint32_t t[kSampleRank] = {};
-            for (int i = 0; i < Ls; ++i) {
-                uint32_t v = aux[threadIdx.x * Ls + i];
+            for (int i = lane; i < Ls; i += 64) {
+                uint32_t v = aux[c * Ls + i];
 #pragma unroll
                 for (int r = 0; r < kSampleRank; ++r) {
                     const uint32_t a = max(t[r], v);
@@ -699,7 +720,17 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
                     t[r] = a;
                 }
             }
-            colS[threadIdx.x] = binade_exact(t[kSampleRank - 1]) + kHeadroom;
+            uint32_t top = 0;
+            for (int r = 0; r < kSampleRank; ++r) {
+                top = wave_max(t[0]);
+                const uint64_t holders = __builtin_amdgcn_ballot_w64(t[0] == top);
+                if (lane == (int)__builtin_ctzll(holders)) {
+#pragma unroll
+                    for (int i = 0; i + 1 < kSampleRank; ++i) t[i] = t[i + 1];
+                    t[kSampleRank - 1] = 0;
+                }
+            }
+            if (lane == 0) colS[c] = binade_exact(top) + kHeadroom;
         }
         __syncthreads();
         int Elo = colS[2 * q], Ehi = colS[2 * q + 1];
@@ -755,81 +786,121 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
     }
     __syncthreads();
 
-    // The unit's exact fixed-point sum of entry (lb, o, c), rounded once to FP32.
-    auto decode = [&](uint32_t lb, uint32_t o, uint32_t c) -> float {
-        const uint32_t wi = lds_row_fixed<BG, NT>(lb, o, W) + c;
+    // Each thread keeps one column pair of the tile (cp) and walks bucket rows
+    // o0, o0 + ostep, ... of every local block.
+    constexpr uint32_t NP = NT / 2;
+    const uint32_t cp = threadIdx.x % NP;
+    const uint32_t o0 = threadIdx.x / NP, ostep = blockDim.x / NP;
+    const int cpair = c0 + 2 * (int)cp;                     // first column of the pair in A
+    int S0 = 0, S1 = 0;
+    uint32_t bsh = 0;                                        // B = 2^bsh
+    if (fixed_ok) {
+        S0 = colS[2 * cp];
+        S1 = colS[2 * cp + 1];
+        bsh = (uint32_t)__builtin_ctz(Bfix);
+    }
+    // body(lb, o, b): bucket row o of local block lb, b = its row of SA.
+    auto for_rows = [&](auto&& body) {
+        for (uint32_t lb = 0; lb < (uint32_t)BG; ++lb) {
+            int64_t b = (int64_t)(j0 + lb) * W + o0;
+#pragma unroll 4
+            for (uint32_t o = o0; o < W; o += ostep, b += ostep) body(lb, o, b);
+        }
+    };
+
+    // The unit's exact fixed-point sums of the pair's two entries in bucket row
+    // (lb, o), each rounded once to FP32.  F - K*B + N is evaluated modulo
+    // 2^32: every field sum is below 2^32 and the signed result below 2^30 in
+    // magnitude (K < 2^(10+h), |q| <= 2^(20-h)), so the wrapped difference is
+    // the exact integer.
+    auto decode2 = [&](uint32_t lb, uint32_t o) -> float2 {
+        const uint32_t wi = lds_row_fixed<BG, NT>(lb, o, W) + 2u * cp;
         const uint64_t cv = cnt[lb * W + o];
-        const int64_t kb = (int64_t)(uint32_t)cv * (int64_t)Bfix - (int64_t)(cv >> 32);
-        const int S = colS[c];
-        const int64_t hi = (int64_t)((const uint32_t*)lds)[wi] - kb;
+        const uint32_t kb = ((uint32_t)cv << bsh) - (uint32_t)(cv >> 32);
+        const uint2 f = *(const uint2*)((const uint32_t*)lds + wi);
+        const int32_t a = (int32_t)(f.x - kb), b = (int32_t)(f.y - kb);
         if constexpr (ACC == 2) {
-            const int64_t lo = (int64_t)((const uint32_t*)lds)[nw + wi] - kb;
-            return (float)ldexp((double)(hi * 2097152 + lo), -(S + 21));
+            // value = (a * 2^21 + residual) * 2^-(S + 21); the sum is exact in FP64
+            const uint2 g = *(const uint2*)((const uint32_t*)lds + nw + wi);
+            const double va = __builtin_fma((double)a, 2097152.0, (double)(int32_t)(g.x - kb));
+            const double vb = __builtin_fma((double)b, 2097152.0, (double)(int32_t)(g.y - kb));
+            return make_float2((float)ldexp(va, -(S0 + 21)), (float)ldexp(vb, -(S1 + 21)));
         } else {
-            return ldexpf((float)hi, -S);
+            return make_float2(ldexpf((float)a, -S0), ldexpf((float)b, -S1));
         }
     };
     if (fixed_ok && nout > 0) {
         // Decode the partial to FP32 in place (array 0), then add the outliers.
         // (each entry is read and rewritten by one thread: no other entry shares its words)
-        const uint32_t total = (uint32_t)BG * W * NT;
-        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-            const uint32_t c = e % NT, o = (e / NT) % W, lb = e / (NT * W);
-            const float v = decode(lb, o, c);
-            lds[lds_row_fixed<BG, NT>(lb, o, W) + c] = v;
-        }
+        for_rows([&](uint32_t lb, uint32_t o, int64_t) {
+            *(float2*)(lds + lds_row_fixed<BG, NT>(lb, o, W) + 2u * cp) = decode2(lb, o);
+        });
         __syncthreads();
-        for (uint32_t r = threadIdx.x; r < nout; r += blockDim.x)
-            __hip_atomic_fetch_add(lds + aux[2 * r], __uint_as_float(aux[2 * r + 1]), __ATOMIC_RELAXED,
+        for (uint32_t i = threadIdx.x; i < nout; i += blockDim.x)
+            __hip_atomic_fetch_add(lds + aux[2 * i], __uint_as_float(aux[2 * i + 1]), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         __syncthreads();
     }
-    // Entry (lb, o, c) of the finished partial.
-    auto entry = [&](uint32_t lb, uint32_t o, uint32_t c) -> float {
-        if (fixed_ok) {
-            if (nout == 0) return decode(lb, o, c);
-            return lds[lds_row_fixed<BG, NT>(lb, o, W) + c];
+    // The pair's two entries of the finished partial in bucket row (lb, o).
+    // DEC: the fixed-point sums are decoded here (the common case, compiled
+    // into branch-free flush loops); otherwise the partial holds FP32 values,
+    // decoded in place (fixed layout) or from the float path (whose rows may
+    // start at an odd word).
+    auto entry2 = [&](auto dec_c, uint32_t lb, uint32_t o) -> float2 {
+        if constexpr (decltype(dec_c)::value) {
+            return decode2(lb, o);
+        } else {
+            if (fixed_ok) return *(const float2*)(lds + lds_row_fixed<BG, NT>(lb, o, W) + 2u * cp);
+            const float* e = lds + lds_row<BG, NT>(lb, o, W) + 2u * cp;
+            return make_float2(e[0], e[1]);
         }
-        return lds[lds_row<BG, NT>(lb, o, W) + c];
     };
+    const bool dec = fixed_ok && nout == 0;
 
     // ---- flush the partial into SA -----------------------------------------
+    if (cpair >= p.n) return;
+    const bool has1 = cpair + 1 < p.n;
     const int64_t r0g = p.row_offset + r_begin;             // first global row of the unit
     if (p.mode == 0) {
         float* SA = (float*)p.SA;
-        const uint32_t total = (uint32_t)BG * W * NT;
-        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-            const uint32_t c = e % NT, o = (e / NT) % W, lb = e / (NT * W);
-            const int cc = c0 + (int)c;
-            if (cc >= p.n) continue;
-            const float v = entry(lb, o, c);
-            const int64_t b = (int64_t)(j0 + lb) * W + o;
-            unsafeAtomicAdd(SA + b * p.ldsa + cc, v * p.scale);
-        }
+        auto flush32 = [&](auto dec_c) {
+            for_rows([&](uint32_t lb, uint32_t o, int64_t b) {
+                const float2 v = entry2(dec_c, lb, o);
+                float* dst = SA + b * p.ldsa + cpair;
+                unsafeAtomicAdd(dst, v.x * p.scale);
+                if (has1) unsafeAtomicAdd(dst + 1, v.y * p.scale);
+            });
+        };
+        if (dec) flush32(std::true_type{});
+        else flush32(std::false_type{});
     } else {
         typedef _Float16 h2 __attribute__((ext_vector_type(2)));
         uint16_t* SA = (uint16_t*)p.SA;
-        const uint32_t total = (uint32_t)BG * W * (NT / 2);
-        const uint64_t dn = (uint64_t)p.d * (uint64_t)p.n;
-        for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-            const uint32_t cp = e % (NT / 2), o = (e / (NT / 2)) % W, lb = e / ((NT / 2) * W);
-            const int cc = c0 + 2 * (int)cp;
-            if (cc >= p.n) continue;
-            const int64_t b = (int64_t)(j0 + lb) * W + o;
-            const float v0 = entry(lb, o, 2 * cp), v1 = entry(lb, o, 2 * cp + 1);
-            const uint64_t site = (uint64_t)r0g * dn + (uint64_t)b * (uint64_t)p.n + (uint64_t)cc;
-            uint32_t u0 = 0, u1 = 0;
-            if (p.mode >= 2) {
-                u0 = round_bits(site, p.epoch, p.k0, p.k1);
-                u1 = round_bits(site + 1, p.epoch, p.k0, p.k1);
-            }
-            const uint16_t h0 = quantize(p.mode, v0 * p.scale, u0);
-            // -0.0 leaves the neighbouring half unchanged (x + -0 == x for every x)
-            const uint16_t h1 = (cc + 1 < p.n) ? quantize(p.mode, v1 * p.scale, u1) : (uint16_t)0x8000u;
-            const uint32_t packed = (uint32_t)h0 | ((uint32_t)h1 << 16);
-            h2 hv = __builtin_bit_cast(h2, packed);
-            __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * p.ldsa + cc), hv);
-        }
+        const uint64_t site0 = (uint64_t)r0g * ((uint64_t)p.d * (uint64_t)p.n) + (uint64_t)cpair;
+        // MODE: the rounding rule, fixed per loop in the common case so the
+        // body has no branches (0: taken from p.mode at run time)
+        auto flush16 = [&](auto mode_c, auto dec_c) {
+            constexpr int MODE = decltype(mode_c)::value;
+            const int mode = MODE ? MODE : p.mode;
+            for_rows([&](uint32_t lb, uint32_t o, int64_t b) {
+                const float2 v = entry2(dec_c, lb, o);
+                uint32_t u0 = 0, u1 = 0;
+                if (MODE == 0 ? mode >= 2 : MODE >= 2)
+                    round_bits2(site0 + (uint64_t)b * (uint64_t)p.n, p.epoch, p.k0, p.k1, u0, u1);
+                // the scaled value is rounded to FP32 before its rounding to
+                // FP16 (the opaque copy keeps the two roundings apart)
+                const uint16_t h0 = quantize(mode, as_fp32(v.x * p.scale), u0);
+                // -0.0 leaves the neighbouring half unchanged (x + -0 == x for every x)
+                const uint16_t h1 = has1 ? quantize(mode, as_fp32(v.y * p.scale), u1) : (uint16_t)0x8000u;
+                const uint32_t packed = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                h2 hv = __builtin_bit_cast(h2, packed);
+                __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * p.ldsa + cpair), hv);
+            });
+        };
+        if (!dec) flush16(std::integral_constant<int, 0>{}, std::false_type{});
+        else if (p.mode == 2) flush16(std::integral_constant<int, 2>{}, std::true_type{});
+        else if (p.mode == 3) flush16(std::integral_constant<int, 3>{}, std::true_type{});
+        else flush16(std::integral_constant<int, 1>{}, std::true_type{});
     }
 }
 

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(kContribThreads) void finish16_kernel(const float* 
             u0 = round_bits(q, epoch, k0, k1);
             u1 = round_bits(q + 1, epoch, k0, k1);
         }
-        const uint16_t h0 = quantize(mode, ws[b * n + c] * scale, u0);
-        const uint16_t h1 = two ? quantize(mode, ws[b * n + c + 1] * scale, u1) : (uint16_t)0x8000u;
+        const uint16_t h0 = quantize(mode, as_fp32(ws[b * n + c] * scale), u0);
+        const uint16_t h1 = two ? quantize(mode, as_fp32(ws[b * n + c + 1] * scale), u1) : (uint16_t)0x8000u;
         const h2 hv = __builtin_bit_cast(h2, (uint32_t)h0 | ((uint32_t)h1 << 16));
         __builtin_amdgcn_global_atomic_fadd_v2f16((h2*)(SA + b * ldsa + c), hv);
     }
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kContribThreads) void finish_bf16_kernel(const floa
         const int c = (int)(e - b * n);
         const uint64_t q = site0 + (uint64_t)b * (uint64_t)n + (uint64_t)c;
         const uint32_t u = mode != 4 ? round_bits(q, epoch, k0, k1) : 0u;
-        uint16_t h = quantize_bf16(mode, ws[e] * scale, u);
+        uint16_t h = quantize_bf16(mode, as_fp32(ws[e] * scale), u);
         uint16_t* dst = SA + b * ldsa + c;
         if (accumulate) h = b16_rn(b16_val(*dst) + b16_val(h));
         *dst = h;

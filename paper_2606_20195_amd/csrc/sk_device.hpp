@@ -76,6 +76,27 @@ __device__ __forceinline__ uint32_t round_bits(uint64_t q, uint32_t epoch, uint3
     return word_of(w, (uint32_t)(q & 3)) & 0xFFFFFFu;
 }
 
+// The rounding bits of sites q and q + 1 (one Philox block when both fall in it).
+__device__ __forceinline__ void round_bits2(uint64_t q, uint32_t epoch, uint32_t k0, uint32_t k1, uint32_t& u0,
+                                            uint32_t& u1)
+{
+    const uint64_t call = q >> 2;
+    const uint4 w = philox10(make_uint4((uint32_t)call, (uint32_t)(call >> 32), epoch, kTagRound), k0, k1);
+    const uint32_t i = (uint32_t)(q & 3);
+    u0 = word_of(w, i) & 0xFFFFFFu;
+    u1 = (i != 3u) ? (word_of(w, i + 1u) & 0xFFFFFFu) : round_bits(q + 1, epoch, k0, k1);
+}
+
+// x as a materialised FP32 value: the compiler may not fold the operation
+// that produced it into a following conversion (an FP32 product followed by
+// an FP16 conversion would otherwise become one mixed-precision FMA with a
+// single rounding).
+__device__ __forceinline__ float as_fp32(float x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 // ---- FP32 -> FP16 rounding rules -----------------------------------------
 
 __device__ __forceinline__ uint16_t f16_bits(__half h) { return __half_as_ushort(h); }
