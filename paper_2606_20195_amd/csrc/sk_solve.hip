@@ -163,10 +163,8 @@ template <> __device__ __forceinline__ float hi16<__hip_bfloat16>(uint32_t w) { 
 // vec = false the bytes are read with element-sized loads (any element
 // alignment).  Offsets past the buffer's end read as zero.
 template <typename AT>
-__device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool vec,
-                                           float (&a)[ET<AT>::C])
+__device__ __forceinline__ void load_raw(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool vec, uint32_t (&w)[4])
 {
-    uint32_t w[4];
     if (vec) {
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
         w[0] = q[0];
@@ -184,6 +182,14 @@ __device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t o
             w[e] = (l & 0xFFFFu) | (h << 16);
         }
     }
+}
+
+// The C elements of a raw chunk as FP32.  The row passes keep chunks raw
+// while their loads are in flight (16-bit elements take half the registers)
+// and convert them where they are used.
+template <typename AT>
+__device__ __forceinline__ void unpack(const uint32_t (&w)[4], float (&a)[ET<AT>::C])
+{
     if constexpr (ET<AT>::B == 4) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) a[e] = __uint_as_float(w[e]);
@@ -194,6 +200,16 @@ __device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t o
             a[2 * e + 1] = hi16<AT>(w[e]);
         }
     }
+}
+
+// load_raw then unpack: C elements as FP32.
+template <typename AT>
+__device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool vec,
+                                           float (&a)[ET<AT>::C])
+{
+    uint32_t w[4];
+    load_raw<AT>(rs, off, vec, w);
+    unpack<AT>(w, a);
 }
 
 // ------------------------------------------------------------ row passes
@@ -363,7 +379,7 @@ __device__ void lsqr_start(const RowArgs& p, double* g, double rnorm)
 template <typename AT, int LR, int CP>
 __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
 {
-    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = 1;
+    constexpr int C = ET<AT>::C, B = ET<AT>::B, RW = 64 / LR, U = CP >= 2 ? 1 : (ET<AT>::B == 4 ? 3 : 2);
     extern __shared__ double dsh[];
     __shared__ double xs[kMaxN + 16];          // x in FP64, zero past n
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -397,32 +413,35 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
     double rr = 0.0, aa = 0.0, bb = 0.0;
     const int64_t step = (int64_t)kWaves * RW;
 
-    float aA[U][CP][C], aB[U][CP][C];
+    uint32_t aA[U][CP][4], aB[U][CP][4];
     double bA[U], bB[U];
-    auto load = [&](float (&a)[U][CP][C], double (&bv)[U], int64_t rb) {
+    auto load = [&](uint32_t (&w)[U][CP][4], double (&bv)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
             const bool valid = row < row1;
             const uint32_t off = valid ? (uint32_t)(row - row0) * rowbytes : nrec;
 #pragma unroll
-            for (int pp = 0; pp < CP; ++pp) load_chunk<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, a[uu][pp]);
+            for (int pp = 0; pp < CP; ++pp) load_raw<AT>(rsrc, off + (uint32_t)(col0[pp] * B), vec, w[uu][pp]);
             bv[uu] = valid ? p.b[row] : 0.0;
         }
     };
-    auto use = [&](float (&a)[U][CP][C], const double (&bv)[U], int64_t rb) {
+    auto use = [&](const uint32_t (&w)[U][CP][4], const double (&bv)[U], int64_t rb) {
 #pragma unroll
         for (int uu = 0; uu < U; ++uu) {
             const int64_t row = rb + uu * step + rs;
             const bool valid = row < row1;
+            float a[CP][C];
+#pragma unroll
+            for (int pp = 0; pp < CP; ++pp) unpack<AT>(w[uu][pp], a[pp]);
             double dot = 0.0;
 #pragma unroll
             for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
                 for (int e = 0; e < C; ++e) {
-                    if (mask && col0[pp] + e >= n) a[uu][pp][e] = 0.0f;
+                    if (mask && col0[pp] + e >= n) a[pp][e] = 0.0f;
                     const int c = min(col0[pp] + e, kMaxN + 15);
-                    dot = fma((double)a[uu][pp][e], xs[c], dot);
+                    dot = fma((double)a[pp][e], xs[c], dot);
                 }
             dot = group_sum<LR>(dot);
             const double r = valid ? bv[uu] - dot : 0.0;
@@ -434,9 +453,9 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
                 for (int e = 0; e < C; ++e) {
                     if constexpr (GL) {
                         const int c = col0[pp] + e;
-                        if (c < n) red[wave * n + c] = fma(r, (double)a[uu][pp][e], red[wave * n + c]);
+                        if (c < n) red[wave * n + c] = fma(r, (double)a[pp][e], red[wave * n + c]);
                     } else {
-                        g[pp][e] = fma(r, (double)a[uu][pp][e], g[pp][e]);
+                        g[pp][e] = fma(r, (double)a[pp][e], g[pp][e]);
                     }
                 }
             if (first) {
@@ -444,7 +463,7 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
 #pragma unroll
                 for (int pp = 0; pp < CP; ++pp)
 #pragma unroll
-                    for (int e = 0; e < C; ++e) aa = fma((double)a[uu][pp][e], (double)a[uu][pp][e], aa);
+                    for (int e = 0; e < C; ++e) aa = fma((double)a[pp][e], (double)a[pp][e], aa);
             }
         }
     };
