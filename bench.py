@@ -62,6 +62,8 @@ def parse():
                    help="skip timing the one-atomic-per-contribution scheme against the partial-sum kernels")
     p.add_argument("--leg", default="all", choices=("all", "headline", "batch", "ls", "serve"),
                    help="run one leg only (for per-leg kernel traces); 'all' is the full benchmark")
+    p.add_argument("--shapes", action="store_true",
+                   help="the apply kernel per matrix width n in {8..128} (planned and autotuned schedules)")
     p.add_argument("--families", action="store_true",
                    help="run only the per-family report at the headline size (error and eta against FP64)")
     return p.parse_args()
@@ -259,6 +261,47 @@ def families_leg():
         out[kind] = row
     return {"workload": "A 4194304x64 stored FP16 per family, d=1024, s=4, sketch seed 0; U = orth(A) stored FP32",
             "families": out}
+
+
+def shapes_leg(m=1 << 21):
+    """The apply kernel per matrix width, the batch's shapes one at a time:
+    m x n FP16 N(0,1), n in {8, 16, 32, 64, 128}, d = 4n, s = 4, FP16-RN,
+    the last-level cache evicted before each call; the planned schedule and
+    the autotuned one.  Rows hashed per call = m x column tiles."""
+    import torch
+    from paper_2606_20195_amd import ACC_F16_RN, Sketch, clear_tuning, stream_read
+    stream = torch.cuda.current_stream()
+    evict_buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    fold = torch.zeros(256, dtype=torch.int32, device="cuda")
+    evict = lambda: stream_read(evict_buf, fold)  # noqa: E731
+    gen = torch.Generator(device="cuda")
+    out = {}
+    for n in (8, 16, 32, 64, 128):
+        gen.manual_seed(n)
+        A = torch.randn((m, n), generator=gen, device="cuda", dtype=torch.float32).half()
+        d = 4 * n
+        row = {}
+        for label in ("planned", "tuned"):
+            clear_tuning()
+            sk = Sketch(m, d, 4, 0, ACC_F16_RN)
+            SA = sk.empty_output(n, "cuda")
+            if label == "tuned":
+                sk.tune(A, SA)
+            for _ in range(3):
+                sk.apply(A, SA=SA)
+            per = time_calls(lambda: sk.apply(A, SA=SA, accumulate=True), 20, stream, evict)
+            ms = float(np.mean(per))
+            plan = sk.plan(1, m, n)
+            row[label] = {"kernel_ms": round(ms, 4), "GB/s": round(m * n * 2 / (ms * 1e-3) / 1e9, 1),
+                          "schedule": {k: plan[k] for k in ("col_tile", "block_group", "waves", "chunk_rows")},
+                          "rows_hashed_per_call": m * ((n + plan["col_tile"] - 1) // plan["col_tile"])
+                          if plan["col_tile"] else None}
+        clear_tuning()
+        out["n=%d" % n] = row
+        del A
+        torch.cuda.empty_cache()
+    return {"workload": "A %dx n FP16 N(0,1), d = 4n, s = 4, FP16-RN, per n; kernel time with the "
+                        "last-level cache evicted" % m, "shapes": out}
 
 
 def batch_leg(reps=10):
@@ -640,6 +683,9 @@ def main():
         return
     if args.families:
         print(json.dumps({"families": families_leg()}), flush=True)
+        return
+    if args.shapes:
+        print(json.dumps({"shapes": shapes_leg()}), flush=True)
         return
     if args.leg == "batch":
         print(json.dumps({"batch": batch_leg()}), flush=True)

@@ -288,7 +288,8 @@ int sketch_batch_destroy(sk_batch_handle b);
 
 /*
  * sketch_tune_batch -- time candidate schedules (rows per work item x waves
- * per workgroup) on this batch with real launches (each problem's SA is
+ * per workgroup x column tile: each problem's own, or 32 columns for all) on
+ * this batch with real launches (each problem's SA is
  * overwritten), keep the fastest in the process-wide tuning table under the
  * batch's signature, append it to the JSON file `cache_path` (NULL: no file)
  * and return it in *out (may be NULL).  Errors: as sketch_batch_create.
@@ -297,7 +298,8 @@ int sketch_tune_batch(const sk_problem *probs, int32_t count, const char *cache_
 
 /*
  * sketch_tune_apply -- the same for single sketch_apply calls of this handle
- * on (a_dtype, rows, n): candidates over chunk_rows x waves x block_group;
+ * on (a_dtype, rows, n): candidates over chunk_rows x waves x block_group x
+ * column tile (32, 8, 4 or 2 columns, or the global-atomic workspace path);
  * SA is overwritten.  The winner is used by later sketch_apply calls with the
  * same signature (handle's d, s, rounding; a_dtype; n; rows rounded to a
  * power of two) unless a schedule is forced.  Errors: as sketch_apply.
