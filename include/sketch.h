@@ -66,9 +66,10 @@ typedef struct sk_sketch *sk_handle;
 
 /*
  * Work decomposition of one sketch_apply call.  Rows are cut into units of
- * `chunk_rows` consecutive rows; each unit is summed in FP32 by one workgroup
- * per column tile (and per group of `block_group` SparseStack blocks) and
- * then added into SA once.  In the FP16 modes each unit's partial is scaled
+ * `chunk_rows` consecutive rows; each unit is summed by one workgroup per
+ * column tile (and per group of `block_group` SparseStack blocks) into an
+ * FP32 partial (an integer fixed-point sum in LDS, decoded once) and then
+ * added into SA once.  In the FP16 modes each unit's partial is scaled
  * by fl32(1/sqrt(s)), rounded to FP16 with the handle's rule, and added with
  * FP16 round-to-nearest atomics, so `chunk_rows` fixes the rounding sites:
  * site q of entry (b, c) in the unit starting at global row r0 is
@@ -248,7 +249,9 @@ typedef struct sk_batch *sk_batch_handle;
  * signature, else the default), sorts the problems largest first and uploads
  * their descriptors to the current device.  The problems' A and SA pointers
  * are recorded and must stay valid while the handle is used.  sched fields:
- * chunk_rows (rows per work item), block_group, waves; xcd_remap is ignored.
+ * chunk_rows (rows per work item; default 16384), block_group, waves,
+ * col_tile (0: 8 columns for n <= 16 and 32 otherwise, per problem; or 32 or
+ * 8 for all); xcd_remap is ignored.
  * Errors: SK_EINVAL, SK_EUNSUPPORTED, SK_ENOMEM, SK_EHIP.
  */
 int sketch_batch_create(const sk_problem *probs, int32_t count, const sk_schedule *sched, sk_batch_handle *out);

@@ -130,8 +130,12 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
     pl.col_tiles = (int32_t)((n + pl.nt - 1) / pl.nt);
     const int maxw = apply_max_waves(a_dtype, pl.bg);
     // the most waves the element type allows (16 for 16-bit A, 8 for FP32 A)
-    // measured fastest: more waves keep more LDS atomics in flight
-    const int autow = maxw;
+    // measured fastest for 32-column tiles: more waves keep more LDS atomics
+    // in flight.  Narrow matrices (n <= 16, 8-column tiles) take 8: their
+    // items are short, and two workgroups a CU overlap one's clearing,
+    // sample and flush with the other's stream (n = 16: 0.044 against
+    // 0.072 ms at 2^21 rows)
+    const int autow = (pl.nt == 8 && n <= 16) ? std::min(maxw, 8) : maxw;
     pl.waves = (f && f->waves) ? f->waves : autow;
     // odd n or lda take the scalar-load kernels, built for at most 8 waves
     if (((n | lda) & 1) && pl.waves > 8) pl.waves = 8;
@@ -146,7 +150,14 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         if (pl.chunk_rows > max_chunk)
             return set_error(SK_EUNSUPPORTED, "chunk_rows = %d spans more than 2 GiB", pl.chunk_rows);
     } else {
-        const int64_t wg_per_cu = std::max<int64_t>(1, (int64_t)(dev.lds_max / pl.lds_bytes));
+        // One round of work items fills the GPU: a CU holds as many workgroups
+        // as fit both its LDS and its wave slots (maxw waves at the kernels'
+        // register budget).  More, smaller units only add fixed per-item
+        // work (clearing, the exponent sample, decoding and the flush): with
+        // 16-wave workgroups, 2048-row units at n = 32 measured 1.7x slower
+        // than units four to eight times larger.
+        const int64_t wg_lds = std::max<int64_t>(1, (int64_t)(dev.lds_max / pl.lds_bytes));
+        const int64_t wg_per_cu = std::max<int64_t>(1, std::min<int64_t>(wg_lds, maxw / pl.waves));
         const int64_t target = std::max<int64_t>(1, (int64_t)dev.cus * wg_per_cu / per_unit);
         int64_t chunk = (rows + target - 1) / target;
         chunk = (chunk + 63) / 64 * 64;

@@ -339,7 +339,10 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
     const int maxw = batch_max_waves();
     int waves = use.waves ? use.waves : 8;
     if (waves > maxw) return set_error(SK_EINVAL, "waves = %d exceeds %d for this element type", waves, maxw);
-    const int32_t chunk = use.chunk_rows ? use.chunk_rows : 4096;
+    // 16384-row units unless tuned: longer items amortise each item's fixed
+    // work (clearing, the exponent sample, decoding, the flush); on the
+    // 512-sketch benchmark batch 16384 rows measured 1.15x faster than 4096
+    const int32_t chunk = use.chunk_rows ? use.chunk_rows : 16384;
     const int esz = esize(a_dtype);
 
     std::vector<BatchDesc> descs((size_t)count);
