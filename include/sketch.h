@@ -87,7 +87,13 @@ typedef struct sk_schedule {
                           /* in LDS and waste no lanes when n is small        */
     int32_t global_atomics; /* 1: no LDS partials: the call's contributions   */
                           /* go by FP32 global atomics into a d x n workspace */
-                          /* (the path taken when no tile fits in LDS)        */
+    int32_t gather;       /* 1: no LDS partials and no value atomics: rows    */
+                          /* are listed by bucket (counting sort of the hash) */
+                          /* and one wave per SA row chunk sums its listed    */
+                          /* rows in FP64 into the d x n workspace.  Reads A  */
+                          /* s times; the planner takes it when d/s leaves    */
+                          /* only narrow tiles (or none) in LDS for rows of   */
+                          /* 256 bytes or more, or when no tile fits at all   */
     int32_t reserved[1];  /* must be zero                                     */
 } sk_schedule;
 
@@ -302,7 +308,8 @@ int sketch_tune_batch(const sk_problem *probs, int32_t count, const char *cache_
 /*
  * sketch_tune_apply -- the same for single sketch_apply calls of this handle
  * on (a_dtype, rows, n): candidates over chunk_rows x waves x block_group x
- * column tile (32, 8, 4 or 2 columns, or the global-atomic workspace path);
+ * column tile (32, 8, 4 or 2 columns), and the two workspace paths (FP32
+ * global atomics; the bucket-sorted gather);
  * SA is overwritten.  The winner is used by later sketch_apply calls with the
  * same signature (handle's d, s, rounding; a_dtype; n; rows rounded to a
  * power of two) unless a schedule is forced.  Errors: as sketch_apply.

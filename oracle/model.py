@@ -266,6 +266,36 @@ def apply_f32_one_unit_model(A, d, s, seed, row_offset=0, waves=None, block_grou
     return (c_s32(s) * P).astype(np.float32)
 
 
+def apply_whole_call_model(A, d, s, seed, mode, epoch=0, row_offset=0, SA0=None):
+    """Result of a call summed as ONE unit whose partial is fl32 of the exact
+    sum (the bucket-sorted gather path: every entry of SA is the signed sum of
+    the rows hashed to it, Section 2.2's definition read by bucket).
+
+    P = fl32(sum of sign * A[i, c] over the rows hashed to (b, c)), taken from
+    the FP64 sum; v = fl32(c_s32 * P).  FP32 mode: v, or fl32(SA0 + v) when
+    accumulating.  FP16 modes: v quantised once per entry with rounding `mode`
+    (noise site q = row_offset*d*n + b*n + c, as for any unit starting at
+    global row row_offset), added to SA0 (zeros) with one FP16 RN addition.
+    """
+    check_shape(d, s)
+    A = np.asarray(A)
+    n = A.shape[1]
+    P = apply_f64(A, d, s, seed, row_offset, scale=1.0).astype(np.float32)
+    v = (c_s32(s) * P).astype(np.float32)
+    if mode == ACC_F32:
+        if SA0 is None:
+            return v
+        return (np.asarray(SA0, dtype=np.float32) + v).astype(np.float32)
+    u = None
+    if mode in (ACC_F16_SR, ACC_F16_DITHER):
+        site = (np.uint64(row_offset) * np.uint64(d * n) + np.arange(d, dtype=np.uint64)[:, None] * np.uint64(n)
+                + np.arange(n, dtype=np.uint64)[None, :])
+        u = round_u24(seed, epoch, site)
+    qv = quantize(mode, v, u)
+    acc = np.zeros((d, n), dtype=np.float16) if SA0 is None else np.asarray(SA0, dtype=np.float16)
+    return f16_add(acc, qv)
+
+
 def contribution_sites(rows, j, n, s):
     """Rounding-noise sites of the per-contribution scheme: q = (i*s + j)*n + c
     for global rows i (array), block j and every column c."""

@@ -168,10 +168,12 @@ class Sketch:
         return sch.as_dict()
 
     def set_schedule(self, chunk_rows=0, block_group=0, waves=0, xcd_remap=1, per_contribution=0, col_tile=0,
-                     global_atomics=0):
+                     global_atomics=0, gather=0):
         """per_contribution=1: one global atomic per contribution (the paper's
-        kernel scheme, a slow reference); the other fields are then ignored."""
-        sch = Schedule(chunk_rows, block_group, waves, xcd_remap, per_contribution, col_tile, global_atomics)
+        kernel scheme, a slow reference); the other fields are then ignored.
+        global_atomics=1 / gather=1: the d x n FP32 workspace paths (FP32
+        atomics, or rows listed by bucket and summed in FP64)."""
+        sch = Schedule(chunk_rows, block_group, waves, xcd_remap, per_contribution, col_tile, global_atomics, gather)
         check(self._lib.sketch_set_schedule(self._h, ctypes.byref(sch)), "sketch_set_schedule")
 
     def clear_schedule(self):

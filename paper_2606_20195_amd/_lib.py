@@ -34,12 +34,12 @@ class Schedule(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int32), ("block_group", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("per_contribution", ctypes.c_int32), ("col_tile", ctypes.c_int32),
-                ("global_atomics", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("global_atomics", ctypes.c_int32), ("gather", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return dict(chunk_rows=self.chunk_rows, block_group=self.block_group, waves=self.waves,
                     xcd_remap=self.xcd_remap, per_contribution=self.per_contribution, col_tile=self.col_tile,
-                    global_atomics=self.global_atomics)
+                    global_atomics=self.global_atomics, gather=self.gather)
 
 
 class Problem(ctypes.Structure):

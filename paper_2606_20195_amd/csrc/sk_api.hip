@@ -90,6 +90,18 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         *out = g;
         return SK_OK;
     }
+    if (f && f->gather) {
+        if (!gather_fits(h->d, n, rows, h->s))
+            return set_error(SK_EUNSUPPORTED, "the gather's 32-bit lists do not hold %lld rows x s = %d",
+                             (long long)rows, h->s);
+        Plan g;
+        g.global = true;
+        g.gather = true;
+        *out = g;
+        return SK_OK;
+    }
+    const int64_t row_bytes = n * (int64_t)elem_size(a_dtype);
+    const bool gather_ok = gather_fits(h->d, n, rows, h->s);
     // FP32 partials (two fields per element) for FP32 and BF16 output
     const bool dual = h->rounding == SK_ACC_F32 || h->rounding >= SK_ACC_BF16_RN;
     Plan pl;
@@ -119,9 +131,30 @@ int make_plan(const sk_sketch* h, int32_t a_dtype, int64_t rows, int64_t n, int6
         if (want_nt || want_bg)
             return set_error(SK_EUNSUPPORTED, "no kernel for col_tile %d, block_group %d fits %lld bucket rows in LDS",
                              want_nt, want_bg, (long long)W);
-        // no block fits in LDS: FP32 workspace path (sketch_apply)
+        // No block fits in LDS: the whole call goes to the FP32 workspace,
+        // by the bucket-sorted gather for rows of 64 bytes or more, else by
+        // FP32 atomics (narrow rows make the gather's list traffic and its
+        // 4-byte reads cost more than one atomic per contribution).
         Plan g;
         g.global = true;
+        g.gather = !f && gather_ok && row_bytes >= 64;
+        *out = g;
+        return SK_OK;
+    }
+    // With rows of 256 bytes or more, reading each row s times by bucket
+    // costs less than a tile narrower than the width calls for (d/s too large
+    // for it in LDS), which hashes every row once per column tile, and than
+    // one-block FP32 partials (two fields per element, s passes over A).
+    // Table 1 sizes, 2^21 x 1024 FP32: d/n = 8 and 16 with 8- and 2-column
+    // tiles 19 and 37 ms, gather 6.3 and 6.5 ms; FP32 mode at d/n = 2 with
+    // one-block 32-column tiles 7.6 ms, gather 6.4 ms.  FP16 partials with
+    // one block keep the tiles (d/n = 4: 3.9 against 6.2 ms): a unit's s
+    // passes run together and share its rows through the caches.
+    if (!f && gather_ok && row_bytes >= 256 &&
+        (pl.nt < ((n <= 16) ? 8 : 32) || (dual && pl.bg == 1 && h->s > 1))) {
+        Plan g;
+        g.global = true;
+        g.gather = true;
         *out = g;
         return SK_OK;
     }
@@ -191,6 +224,9 @@ static int check_schedule(const sk_schedule* s)
     if (s->global_atomics != 0 && s->global_atomics != 1) return set_error(SK_EINVAL, "global_atomics must be 0 or 1");
     if (s->global_atomics && s->per_contribution)
         return set_error(SK_EINVAL, "global_atomics and per_contribution exclude each other");
+    if (s->gather != 0 && s->gather != 1) return set_error(SK_EINVAL, "gather must be 0 or 1");
+    if (s->gather && (s->global_atomics || s->per_contribution))
+        return set_error(SK_EINVAL, "gather excludes global_atomics and per_contribution");
     if (s->reserved[0]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     return SK_OK;
 }
@@ -315,7 +351,8 @@ int sketch_plan(sk_handle h, int32_t a_dtype, int64_t rows, int64_t n, sk_schedu
     out->xcd_remap = pl.xcd_remap;
     out->per_contribution = pl.direct ? 1 : 0;
     out->col_tile = pl.bg ? pl.nt : 0;
-    out->global_atomics = pl.global ? 1 : 0;
+    out->global_atomics = (pl.global && !pl.gather) ? 1 : 0;
+    out->gather = pl.gather ? 1 : 0;
     return SK_OK;
 }
 
@@ -383,6 +420,17 @@ static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     if (!a.aligned && pl.waves > 8) pl.waves = 8;
     const float cs = value_scale32(h->s);
 
+    // The bucket-sorted gather's lists may not fit a caller's scratch: then
+    // the planner's choice falls back to FP32 atomics into the d x n sum.
+    const size_t sum_floats = (size_t)h->d * (size_t)n;
+    if (pl.gather && ext_ws && plan_ws_floats(pl, h->d, n, rows, h->s) > ext_floats) {
+        if (h->forced && h->sched.gather)
+            return set_error(SK_EINVAL, "the gather's workspace of %zu floats exceeds the %zu-float scratch",
+                             plan_ws_floats(pl, h->d, n, rows, h->s), ext_floats);
+        pl.gather = false;
+    }
+    const size_t ws_need = pl.gather ? plan_ws_floats(pl, h->d, n, rows, h->s) : sum_floats;
+
     // d x n FP32 workspace held by the handle (allocated on first need)
     float* ws = nullptr;
     auto ensure_ws = [&](size_t need) -> int {
@@ -407,20 +455,27 @@ static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
         ws = h->ws;
         return SK_OK;
     };
+    // ws = the unscaled FP32 sum of the call: by the gather, else cleared and
+    // filled by FP32 atomics (global) or the LDS partials' FP32 flush
+    auto sum_into_ws = [&]() -> hipError_t {
+        a.SA = ws;
+        a.ldsa = n;
+        a.mode = 0;
+        a.scale = 1.0f;
+        if (pl.gather)   // counters, offsets and lists follow the sum
+            return launch_gather(a_dtype, a, ws, (uint32_t*)(ws + (sum_floats + 63) / 64 * 64), st);
+        hipError_t e2 = launch_fill(ws, 4, h->d, n, n, st);
+        if (e2 != hipSuccess) return e2;
+        return pl.global ? launch_contrib(a_dtype, a, st) : launch_apply(a_dtype, pl, a, st);
+    };
     if (bf16) {
         // FP32 sum of the whole call in the workspace, one BF16 rounding per entry
         if (rows == 0) {
             if (!accumulate && (e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess) return hip_fail(e, "fill SA");
             return SK_OK;
         }
-        if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
-        if ((e = launch_fill(ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
-        a.SA = ws;
-        a.ldsa = n;
-        a.mode = 0;
-        a.scale = 1.0f;
-        e = pl.global ? launch_contrib(a_dtype, a, st) : launch_apply(a_dtype, pl, a, st);
-        if (e != hipSuccess) return hip_fail(e, "apply kernel");
+        if ((rc = ensure_ws(ws_need))) return rc;
+        if ((e = sum_into_ws()) != hipSuccess) return hip_fail(e, "apply kernel");
         e = launch_finish_bf16(ws, h->d, (int32_t)n, (uint16_t*)SA, ldsa, h->rounding, cs,
                                (uint64_t)row_offset * (uint64_t)h->d * (uint64_t)n, round_epoch, a.k0, a.k1,
                                accumulate, st);
@@ -428,19 +483,15 @@ static int apply_impl(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     }
     if (pl.global) {
         // d/s bucket rows beyond LDS: the whole call is one unit, summed
-        // unscaled in an FP32 workspace with FP32 atomics, then finished once.
+        // unscaled in an FP32 workspace (FP64 sums of the bucket-sorted
+        // gather, or FP32 atomics), then finished once.
         if (rows == 0) {
             if (!accumulate && (e = launch_fill(SA, f16 ? 2 : 4, h->d, n, ldsa, st)) != hipSuccess)
                 return hip_fail(e, "fill SA");
             return SK_OK;
         }
-        if ((rc = ensure_ws((size_t)h->d * (size_t)n))) return rc;
-        if ((e = launch_fill(ws, 4, h->d, n, n, st)) != hipSuccess) return hip_fail(e, "fill workspace");
-        a.SA = ws;
-        a.ldsa = n;
-        a.mode = 0;
-        a.scale = 1.0f;
-        if ((e = launch_contrib(a_dtype, a, st)) != hipSuccess) return hip_fail(e, "workspace kernel");
+        if ((rc = ensure_ws(ws_need))) return rc;
+        if ((e = sum_into_ws()) != hipSuccess) return hip_fail(e, pl.gather ? "gather kernels" : "workspace kernel");
         if (f16) {
             if (!accumulate && (e = launch_fill(SA, 2, h->d, n, ldsa, st)) != hipSuccess)
                 return hip_fail(e, "fill SA");

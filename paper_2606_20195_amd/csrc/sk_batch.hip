@@ -123,6 +123,7 @@ int parse_tuning(const std::string& text, std::vector<std::pair<std::string, Tun
                             else if (f == "xcd_remap") te.sched.xcd_remap = (int32_t)v;
                             else if (f == "col_tile") te.sched.col_tile = (int32_t)v;
                             else if (f == "global_atomics") te.sched.global_atomics = (int32_t)v;
+                            else if (f == "gather") te.sched.gather = (int32_t)v;
                             else if (f == "ms") te.ms = v;
                         }
                     } while (c.eat(','));
@@ -172,9 +173,9 @@ int save_tuning(const char* path)
     for (auto& kv : table()) {
         const sk_schedule& s = kv.second.sched;
         fprintf(f, "%s\n  {\"key\": \"%s\", \"chunk_rows\": %d, \"block_group\": %d, \"waves\": %d, \"xcd_remap\": %d, "
-                   "\"col_tile\": %d, \"global_atomics\": %d, \"ms\": %.6f}",
+                   "\"col_tile\": %d, \"global_atomics\": %d, \"gather\": %d, \"ms\": %.6f}",
                 first ? "" : ",", kv.first.c_str(), s.chunk_rows, s.block_group, s.waves, s.xcd_remap, s.col_tile,
-                s.global_atomics, kv.second.ms);
+                s.global_atomics, s.gather, kv.second.ms);
         first = false;
     }
     fprintf(f, "\n]}\n");
@@ -281,8 +282,8 @@ int batch_plan(const sk_problem* probs, int32_t count, const sk_schedule* sched,
             return set_error(SK_EUNSUPPORTED, "per-contribution schedules apply to single sketches only");
         if (sched->col_tile && sched->col_tile != 32 && sched->col_tile != 8)
             return set_error(SK_EINVAL, "batches take col_tile 0 (per problem), 32 or 8");
-        if (sched->global_atomics)
-            return set_error(SK_EUNSUPPORTED, "global-atomic schedules apply to single sketches only");
+        if (sched->global_atomics || sched->gather)
+            return set_error(SK_EUNSUPPORTED, "global-atomic and gather schedules apply to single sketches only");
         if (sched->reserved[0]) return set_error(SK_EINVAL, "reserved schedule fields must be zero");
     }
     int rc;
@@ -653,26 +654,28 @@ int sketch_tune_apply(sk_handle h, const void* A, int32_t a_dtype, int64_t rows,
     sk_schedule best{};
     double best_ms = 1e30;
     int rc = SK_OK;
-    // column tile x blocks per workgroup x rows per unit x waves, and the
-    // global-atomic path (LDS partials against atomics per contribution)
-    static const int32_t kTiles[5] = {32, 8, 4, 2, 0};   // 0: the global-atomic path
-    for (int32_t ti = 0; ti < 5; ++ti) {
+    // column tile x blocks per workgroup x rows per unit x waves, and the two
+    // workspace paths: FP32 atomics per contribution, and the bucket-sorted
+    // gather (LDS partials against atomics against reading A s times)
+    static const int32_t kTiles[6] = {32, 8, 4, 2, 0, -1};   // 0: global atomics, -1: gather
+    for (int32_t ti = 0; ti < 6; ++ti) {
         const int32_t nt = kTiles[ti];
       for (int32_t bg : {1, 2, 4, 8}) {
         if (h->s % bg) continue;
-        if (nt ? !apply_tile_ok(nt, bg) : bg != 1) continue;
+        if (nt > 0 ? !apply_tile_ok(nt, bg) : bg != 1) continue;
         for (int32_t chunk : {0, 2048, 4096, 8192, 16384, 32768}) {
-            if (!nt && chunk) continue;
+            if (nt <= 0 && chunk) continue;
             for (int32_t waves : {4, 8, 16}) {
-                if (waves > maxw || (!nt && waves != 4)) continue;
-                if (nt && waves > apply_max_waves(a_dtype, bg)) continue;
+                if (waves > maxw || (nt <= 0 && waves != 4)) continue;
+                if (nt > 0 && waves > apply_max_waves(a_dtype, bg)) continue;
                 sk_schedule s{};
-                s.block_group = nt ? bg : 0;
+                s.block_group = nt > 0 ? bg : 0;
                 s.chunk_rows = chunk;
-                s.waves = nt ? waves : 0;
+                s.waves = nt > 0 ? waves : 0;
                 s.xcd_remap = 1;
-                s.col_tile = nt;
-                s.global_atomics = nt ? 0 : 1;
+                s.col_tile = nt > 0 ? nt : 0;
+                s.global_atomics = nt == 0 ? 1 : 0;
+                s.gather = nt < 0 ? 1 : 0;
                 tmp.sched = s;
                 tmp.forced = true;
                 rc = sketch_apply(&tmp, A, a_dtype, rows, n, lda, 0, SA, ldsa, 0, 0, stream);

@@ -49,6 +49,7 @@ struct Plan {
     size_t lds_bytes = 0;
     bool direct = false;     // one global atomic per contribution
     bool global = false;     // d/s too large for LDS partials: FP32 workspace of the whole call
+    bool gather = false;     // the workspace filled by the bucket-sorted gather (implies global)
 };
 
 // LDS bytes of one work item: bg blocks of W bucket rows of nt columns.
@@ -100,6 +101,18 @@ hipError_t batched_bf16(int bg, bool vec, bool dual, const BatchDesc *descs, int
                         uint32_t *counter, int grid, int waves, size_t lds_bytes, hipStream_t st);
 // One global atomic per contribution (args.mode: 0 FP32 SA, 1..3 FP16 SA).
 hipError_t launch_contrib(int a_dtype, const ApplyArgs &args, hipStream_t st);
+// Bucket-sorted gather (sk_gather.hip): 32-bit words of its counters, offsets
+// and lists beyond the d x n sum; whether a call's shape fits its 32-bit lists
+// and its grid.
+size_t gather_aux_words(int64_t d, int64_t rows, int32_t s);
+bool gather_fits(int64_t d, int64_t n, int64_t rows, int32_t s);
+// ws (d x n FP32, ld n) = the unscaled sum of the call; aux holds
+// gather_aux_words(d, rows, s) words.
+hipError_t launch_gather(int a_dtype, const ApplyArgs &args, float *ws, uint32_t *aux, hipStream_t st);
+// FP32 words of the workspace a plan needs: d x n for the workspace paths,
+// plus the gather's lists (offset 256-byte aligned), else 0.
+size_t plan_ws_floats(const Plan &pl, int64_t d, int64_t n, int64_t rows, int32_t s);
+
 // SA (BF16, ld ldsa) = (or += with one BF16 RN add) the BF16 rounding of fl32(scale * ws).
 hipError_t launch_finish_bf16(const float *ws, int64_t d, int32_t n, uint16_t *SA, int64_t ldsa, int32_t mode,
                               float scale, uint64_t site0, uint32_t epoch, uint32_t k0, uint32_t k1, bool accumulate,

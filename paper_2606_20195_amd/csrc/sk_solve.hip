@@ -1563,6 +1563,7 @@ struct SolveJob {
     size_t oM = 0, o16 = 0, ob32 = 0, ou = 0, oP = 0, oPT = 0, otau = 0, ot = 0, ov = 0, ow = 0, oy = 0, opart = 0,
            ost = 0, otk = 0, oTq = 0, total = 0;
     size_t ows = kNoWs, owsb = kNoWs;  // sketch workspaces in the block (large d/s), or none
+    size_t ws_floats = 0, wsb_floats = 0;   // their sizes in FP32 words (with the gather's lists)
     int32_t qr_blocks = 1;              // row blocks of a two-level QR (d above kQRRows)
     int64_t qr_rows = 0;                // rows per block
     size_t oZ = 0;                      // the stacked triangles [R_1 c_1; ...; R_B c_B]
@@ -1696,9 +1697,10 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     {
         DeviceInfo dv = dev;
         Plan pa, pb;
-        j->ows = (make_plan(&j->S, a_dtype, m, n, lda, dv, &pa) == SK_OK && pa.global) ? take((size_t)d * n * 4)
-                                                                                        : kNoWs;
-        j->owsb = (make_plan(&j->Sb, SK_F32, m, 1, 1, dv, &pb) == SK_OK && pb.global) ? take((size_t)d * 4) : kNoWs;
+        j->ws_floats = (make_plan(&j->S, a_dtype, m, n, lda, dv, &pa) == SK_OK) ? plan_ws_floats(pa, d, n, m, S.s) : 0;
+        j->wsb_floats = (make_plan(&j->Sb, SK_F32, m, 1, 1, dv, &pb) == SK_OK) ? plan_ws_floats(pb, d, 1, m, S.s) : 0;
+        j->ows = j->ws_floats ? take(j->ws_floats * 4) : kNoWs;
+        j->owsb = j->wsb_floats ? take(j->wsb_floats * 4) : kNoWs;
         set_error(SK_OK, "");
     }
     j->total = off;
@@ -1802,9 +1804,9 @@ int job_start(SolveJob* j, void* device_base, hipStream_t st)
     ra.st = (SolveState*)(base + j->ost);
     ra.ticket = (uint32_t*)(base + j->otk);
     j->S.ws = j->ows != kNoWs ? (float*)(base + j->ows) : nullptr;
-    j->S.ws_floats = j->ows != kNoWs ? (size_t)j->S.d * (size_t)j->n : 0;
+    j->S.ws_floats = j->ows != kNoWs ? j->ws_floats : 0;
     j->Sb.ws = j->owsb != kNoWs ? (float*)(base + j->owsb) : nullptr;
-    j->Sb.ws_floats = j->owsb != kNoWs ? (size_t)j->Sb.d : 0;
+    j->Sb.ws_floats = j->owsb != kNoWs ? j->wsb_floats : 0;
     j->k = 0;
     j->launched = 0;
     j->steps = 0;

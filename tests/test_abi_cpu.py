@@ -106,6 +106,11 @@ def test_schedule_validation(lib):
     assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 2))) == _lib.EINVAL
     assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 1, 0, 1))) == _lib.EINVAL
     assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 1))) == 0
+    # the bucket-sorted gather: 0 or 1, alone among the workspace paths
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 0, 2))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 1, 1))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 1, 0, 0, 1))) == _lib.EINVAL
+    assert lib.sketch_set_schedule(h, ctypes.byref(S(0, 0, 0, 1, 0, 0, 0, 1))) == 0
     assert lib.sketch_set_schedule(h, ctypes.byref(S(4096, 4, 8, 0))) == 0
     assert lib.sketch_set_schedule(h, None) == 0
     lib.sketch_destroy(h)

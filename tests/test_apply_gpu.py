@@ -265,10 +265,12 @@ def test_full_size_coherent_and_spikes_fp16():
 def test_large_bucket_counts_plan_narrow_tiles_then_the_workspace():
     p = Sketch(100000, 4096, 1, 3, ACC_F16_RN).plan(1, 100000, 64)
     assert p["block_group"] == 1 and p["col_tile"] in (4, 2) and p["global_atomics"] == 0
-    p = Sketch(100000, 24576, 4, 3, ACC_F32).plan(0, 100000, 1024)          # Table 1 at d/n = 24
-    assert p["block_group"] == 1 and p["col_tile"] == 2
-    p = Sketch(100000, 1 << 17, 1, 3, ACC_F16_RN).plan(1, 100000, 64)       # 131072 bucket rows
+    p = Sketch(100000, 24576, 4, 3, ACC_F32).plan(0, 100000, 16)            # d/s = 6144, narrow rows
+    assert p["block_group"] == 1 and p["col_tile"] == 2 and p["gather"] == 0
+    p = Sketch(100000, 1 << 17, 1, 3, ACC_F16_RN).plan(1, 100000, 16)       # 131072 bucket rows
     assert p["block_group"] == 0 and p["global_atomics"] == 1
+    p = Sketch(100000, 1 << 17, 1, 3, ACC_F16_RN).plan(1, 100000, 64)       # 128-byte rows: the gather
+    assert p["block_group"] == 0 and p["gather"] == 1
     p = Sketch(100000, 1024, 4, 3, ACC_F16_RN).plan(1, 100000, 64)
     assert p["block_group"] == 4 and p["col_tile"] == 32
     p = Sketch(100000, 64, 4, 3, ACC_F16_RN).plan(1, 100000, 16)

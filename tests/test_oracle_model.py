@@ -4,7 +4,7 @@ import numpy as np
 import workloads
 from oracle import model, quant
 from oracle.philox import philox_scalar
-from oracle.sketch import TAG_ROUND, apply_f64
+from oracle.sketch import TAG_ROUND, apply_f64, hash_rows
 
 
 def test_f32_exact_int_matches_fp64_when_representable():
@@ -150,3 +150,46 @@ def test_dual_fields_carry_the_residual():
     assert np.max(np.abs(P - exact) / np.maximum(np.abs(exact), 1.0)) <= 2.0 ** -23
     (P1, _, _, _), _, _ = _item(X, dual=False)
     assert np.max(np.abs(P1 - exact)) > np.max(np.abs(P - exact))
+
+
+def test_whole_call_model_on_integers_is_the_exact_one_unit_result():
+    # integer sums are exact in every model: the whole-call model must agree
+    # with the FP32 exact-integer result and with the fixed-point unit model
+    # run with one unit spanning the call
+    A = workloads.integers(4000, 10, 7, lim=5)
+    d, s = 96, 3
+    assert np.array_equal(model.apply_whole_call_model(A, d, s, 8, model.ACC_F32),
+                          model.apply_f32_exact_int(A, d, s, 8))
+    sa0 = np.full((d, 10), 0.5, dtype=np.float32)
+    assert np.array_equal(model.apply_whole_call_model(A, d, s, 8, model.ACC_F32, SA0=sa0),
+                          model.apply_f32_exact_int(A, d, s, 8, SA0=sa0))
+    for mode in (model.ACC_F16_RN, model.ACC_F16_SR, model.ACC_F16_DITHER):
+        got = model.apply_whole_call_model(A, d, s, 8, mode, epoch=3, row_offset=100)
+        ref = model.apply_f16_model(A, d, s, 8, mode, 3, chunk_rows=4000, row_offset=100)
+        assert np.array_equal(got.view(np.uint16), ref.view(np.uint16)), mode
+
+
+def test_whole_call_model_brute_force_on_one_row():
+    # one row: entry (b_j, c) holds fl32(c_s * sign_j * x_c), rounded to FP16
+    # to nearest by numpy's own conversion; every other entry is zero
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((1, 7)).astype(np.float32)
+    d, s, r0 = 40, 4, 123
+    b, sg = hash_rows(9, [r0], d, s)
+    cs = np.float32(1.0 / np.sqrt(4.0))
+    want32 = np.zeros((d, 7), dtype=np.float32)
+    for j in range(s):
+        want32[b[0, j]] = (cs * (np.float32(sg[0, j]) * x[0])).astype(np.float32)
+    got32 = model.apply_whole_call_model(x, d, s, 9, model.ACC_F32, row_offset=r0)
+    assert np.array_equal(got32, want32)
+    got16 = model.apply_whole_call_model(x, d, s, 9, model.ACC_F16_RN, row_offset=r0)
+    assert np.array_equal(got16.view(np.uint16), want32.astype(np.float16).view(np.uint16))
+
+
+def test_whole_call_model_gaussian_is_the_fp32_rounding_of_fp64():
+    A = workloads.gaussian(3000, 5, 11, np.float32)
+    d, s = 64, 8
+    got = model.apply_whole_call_model(A, d, s, 2, model.ACC_F32)
+    f64 = apply_f64(A, d, s, 2)
+    # fl32 of the unscaled sum, then fl32 of c_s times it: within 2^-23 relative
+    assert np.allclose(got, f64, rtol=2 ** -22, atol=0)

@@ -243,19 +243,23 @@ def test_solve_full_size_coherent_fp16():
     assert np.linalg.norm(x - x_opt) <= 1e-8 * np.linalg.norm(x_opt)
 
 
-@pytest.mark.parametrize("global_atomics", [0, 1])
-def test_solve_with_a_large_ds_sketch(global_atomics):
-    # d/s = 2400 bucket rows: 8-column tiles in LDS, or (forced) the FP32
-    # workspace path, whose workspace lies in the solve's own block
+@pytest.mark.parametrize("path", ["gather", "tiles", "atomics"])
+def test_solve_with_a_large_ds_sketch(path):
+    # d/s = 2400 bucket rows: the planner's bucket-sorted gather, or (forced)
+    # 8-column tiles in LDS or FP32 atomics; the workspace paths' workspace
+    # (and the gather's lists) lie in the solve's own block
     m, n, d = 60000, 300, 2400
     A = workloads.gaussian(m, n, 71, np.float16)
     b = A.astype(np.float64) @ workloads.rng(72).standard_normal(n) + 1e-6 * workloads.rng(73).standard_normal(m)
     sk = Sketch(m, d, 1, 5, ACC_F16_RN)
-    if global_atomics:
+    if path == "atomics":
         sk.set_schedule(global_atomics=1)
-        assert sk.plan(1, m, n)["block_group"] == 0
-    else:
+        assert sk.plan(1, m, n)["global_atomics"] == 1
+    elif path == "tiles":
+        sk.set_schedule(col_tile=8)
         assert sk.plan(1, m, n)["col_tile"] == 8
+    else:
+        assert sk.plan(1, m, n)["gather"] == 1
     x, info = sk.solve(torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda())
     assert info["converged"] == 1
     assert ne_criterion(A, b, x.cpu().numpy()) <= 1.5e-10

@@ -37,6 +37,7 @@ GLOBAL = dict(global_atomics=1)
     (ACC_F32, 4096, 1, GLOBAL),           # the global-atomic path: workspace of the whole call
     (ACC_F16_DITHER, 8192, 2, GLOBAL),    # the same with one FP16 rounding per entry
     (ACC_BF16_SR, 256, 4, None),          # BF16 output: FP32 sum of the call, then one rounding
+    (ACC_F32, 16384, 4, dict(gather=1)),  # the bucket-sorted gather: sum and lists in the scratch
 ])
 def test_noalloc_matches_apply_on_two_calls(rounding, d, s, sched):
     for rows, n in ((30000, 48), (9000, 20)):          # second call smaller
