@@ -563,7 +563,7 @@ def ls_rows(A, b, ratios, seed, tag):
             kappa = float(torch.sqrt(ev[-1] / ev[0]).item()) if ev[0] > 0 else float("inf")
             del X, ev, SA
             plan = sk.plan(0, m, n)
-            path = "workspace" if plan["block_group"] == 0 else "tiles%d" % plan["col_tile"]
+            path = ("gather" if plan["gather"] else "atomics") if plan["block_group"] == 0 else "tiles%d" % plan["col_tile"]
             x, info = sk.solve(A, b, raise_on_notconv=False)
             row = {"problem": tag, "d_over_n": r, "method": name, "sketch_path": path,
                    "sketch_and_solve_ms": round(info["ms_sketch"] + info["ms_factor"], 3),

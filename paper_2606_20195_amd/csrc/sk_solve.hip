@@ -307,6 +307,20 @@ __device__ void matvec_cols(const float* S, int64_t lds_, int n, const double* i
     __syncthreads();
 }
 
+// First row of the next block of `rows` rows of the workgroup's range, from
+// the workgroup's block counter (one LDS atomic per wave, lane 0's result
+// read by every lane).  Row passes take their blocks this way, so the waves of
+// a workgroup stream until its rows run out and finish within one block of
+// each other: with blocks dealt out in a fixed order, the first wave
+// measured some 60 us (a quarter of the pass) ahead of the workgroup's last.
+__device__ __forceinline__ int64_t next_block(uint32_t* ctr, int lane, int64_t row0, int64_t rows)
+{
+    uint32_t v = 0u;
+    if (lane == 0) v = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    v = (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+    return row0 + (int64_t)v * rows;
+}
+
 // True in exactly one workgroup, the last to finish; partials written before
 // the call are visible to it.  Each wave first waits for its own stores to be
 // acknowledged; after the barrier one thread takes a ticket with an
@@ -402,6 +416,8 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
         for (int e = 0; e < C; ++e)
             if constexpr (!GL) g[pp][e] = 0.0;
     }
+    __shared__ uint32_t blk_ctr;
+    if (tid == 0) blk_ctr = 0u;
     __syncthreads();
     const int64_t row0 = (int64_t)blockIdx.x * p.rpw;
     const int64_t row1 = row0 >= p.m ? row0 : (row0 + p.rpw < p.m ? row0 + p.rpw : p.m);
@@ -411,7 +427,9 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
         (void*)((const char*)p.A + row0 * (int64_t)rowbytes), (short)0, (int)nrec, 0x00020000);
     const bool vec = p.vec != 0, mask = p.mask != 0, first = p.first != 0;
     double rr = 0.0, aa = 0.0, bb = 0.0;
-    const int64_t step = (int64_t)kWaves * RW;
+    // blocks of U * RW consecutive rows, dealt out by the workgroup's counter
+    const int64_t step = RW;
+    auto next = [&]() { return next_block(&blk_ctr, lane, row0, (int64_t)U * RW); };
 
     uint32_t aA[U][CP][4], aB[U][CP][4];
     double bA[U], bB[U];
@@ -467,19 +485,22 @@ __global__ __launch_bounds__(kT) void resid_pass(RowArgs p)
             }
         }
     };
-    int64_t rb = row0 + (int64_t)wave * RW;
+    int64_t rb = next();
     if (rb < row1) load(aA, bA, rb);
+    int64_t nx = next();
     while (rb < row1) {
-        int64_t nx = rb + U * step;
         if (nx < row1) load(aB, bB, nx);
+        int64_t nn = nx < row1 ? next() : nx;
         use(aA, bA, rb);
         if (nx >= row1) break;
         rb = nx;
-        nx = rb + U * step;
+        nx = nn;
         if (nx < row1) load(aA, bA, nx);
+        nn = nx < row1 ? next() : nx;
         use(aB, bB, rb);
         if (nx >= row1) break;
         rb = nx;
+        nx = nn;
     }
     // column sums: over the RW row slots of the wave, then over the waves
     if constexpr (!GL) {
@@ -591,14 +612,16 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
         (void*)((const char*)p.A + row0 * (int64_t)rowbytes), (short)0, (int)nrec, 0x00020000);
     const bool vec = p.vec != 0, mask = p.mask != 0;
     float ss = 0.0f;
-    // With BL, a wave takes U * RW consecutive rows at a time (slot uu, row
-    // slot rs = row uu * RW + rs of the block) and moves their u in one load
+    // A wave takes U * RW consecutive rows at a time (slot uu, row slot rs =
+    // row uu * RW + rs of the block).  With BL it moves their u in one load
     // and one store of U * RW lanes, handing values between lanes; otherwise
-    // the slots are kWaves * RW rows apart and every row loads and stores its
-    // own u.
+    // every row loads and stores its own u.
     constexpr bool BL = U * RW <= 64 && U <= LR;
-    const int64_t step = BL ? RW : (int64_t)kWaves * RW;
-    const int64_t wstride = BL ? (int64_t)kWaves * U * RW : U * step;
+    const int64_t step = RW;
+    __shared__ uint32_t blk_ctr;
+    if (tid == 0) blk_ctr = 0u;
+    __syncthreads();
+    auto next = [&]() { return next_block(&blk_ctr, lane, row0, (int64_t)U * RW); };
 
     float aA[U][CP][C], aB[U][CP][C];
     float uA[U], uB[U];
@@ -656,19 +679,25 @@ __global__ __launch_bounds__(kT) void lsqr_pass(RowArgs p)
             if (lane < U * RW && r < row1) p.u[r] = o;
         }
     };
-    int64_t rb = row0 + (int64_t)wave * (BL ? U * RW : RW);
+    // Blocks are handed out in turn from an LDS counter (the index of the
+    // block after next is taken while the current one is used), so the waves
+    // of a workgroup finish together whatever the arbitration between them.
+    int64_t rb = next();
     if (rb < row1) load(aA, uA, rb);
+    int64_t nx = next();
     while (rb < row1) {
-        int64_t nx = rb + wstride;
         if (nx < row1) load(aB, uB, nx);
+        int64_t nn = nx < row1 ? next() : nx;
         use(aA, uA, rb);
         if (nx >= row1) break;
         rb = nx;
-        nx = rb + wstride;
+        nx = nn;
         if (nx < row1) load(aA, uA, nx);
+        nn = nx < row1 ? next() : nx;
         use(aB, uB, rb);
         if (nx >= row1) break;
         rb = nx;
+        nx = nn;
     }
 #pragma unroll
     for (int o = LR; o < 64; o <<= 1)
