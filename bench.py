@@ -60,7 +60,7 @@ def parse():
                    help="run only the coherence sweep (eta against mu(U)) and print its JSON line")
     p.add_argument("--no-paper-scheme", action="store_true",
                    help="skip timing the one-atomic-per-contribution scheme against the partial-sum kernels")
-    p.add_argument("--leg", default="all", choices=("all", "headline", "batch", "ls", "serve"),
+    p.add_argument("--leg", default="all", choices=("all", "headline", "batch", "ls", "serve", "gather"),
                    help="run one leg only (for per-leg kernel traces); 'all' is the full benchmark")
     p.add_argument("--shapes", action="store_true",
                    help="the apply kernel per matrix width n in {8..128} (planned and autotuned schedules)")
@@ -302,6 +302,56 @@ def shapes_leg(m=1 << 21):
         torch.cuda.empty_cache()
     return {"workload": "A %dx n FP16 N(0,1), d = 4n, s = 4, FP16-RN, per n; kernel time with the "
                         "last-level cache evicted" % m, "shapes": out}
+
+
+def gather_leg(m=1 << 21, n=1024, steps=10):
+    """The large-d/s sketches of the paper's Table 1 shape (A = m x n FP32,
+    N(0,1), d/n in {8, 16, 24}, s = 4 and CountSketch s = 1, FP32 and FP16-RN
+    output): the planner's bucket-sorted gather against the narrowest LDS
+    tiles that fit, per call with the last-level cache evicted.  Algorithmic
+    bytes of the gather: s m n 4 (each row read once per block) + d n 4 (the
+    workspace) + 8 m s (list writes and reads); GB/s and the fraction of
+    8 TB/s are quoted on those bytes."""
+    import torch
+    from paper_2606_20195_amd import ACC_F16_RN, ACC_F32, Sketch, stream_read
+    stream = torch.cuda.current_stream()
+    evict_buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    fold = torch.zeros(256, dtype=torch.int32, device="cuda")
+    evict = lambda: stream_read(evict_buf, fold)  # noqa: E731
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    A = torch.randn((m, n), generator=gen, device="cuda", dtype=torch.float32)
+    rows = []
+    for dn in (8, 16, 24):
+        d = dn * n
+        for s, rounding, label in ((4, ACC_F32, "sparsestack_f32"), (4, ACC_F16_RN, "sparsestack_f16rn"),
+                                   (1, ACC_F32, "countsketch_f32")):
+            sk = Sketch(m, d, s, 3, rounding)
+            plan = sk.plan(0, m, n)
+            SA = sk.apply(A)
+            torch.cuda.synchronize()
+            per = time_calls(lambda: sk.apply(A, SA=SA), steps, stream, evict)
+            ms = float(np.mean(per))
+            alg = s * m * n * 4 + d * n * 4 + 8 * m * s
+            row = {"d_over_n": dn, "sketch": label, "path": "gather" if plan["gather"] else "tiles",
+                   "ms": round(ms, 3), "GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
+                   "frac_of_8TBs": round(alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3)}
+            if s == 4 and rounding == ACC_F32:
+                # the narrowest tiles that fit LDS, for comparison (one call: they are slow)
+                for nt in (8, 4, 2):
+                    try:
+                        sk.set_schedule(col_tile=nt, block_group=1)
+                        t = time_calls(lambda: sk.apply(A, SA=SA), 1, stream, evict)
+                        row["tiles%d_ms" % nt] = round(float(t[0]), 2)
+                        break
+                    except Exception:
+                        continue
+            rows.append(row)
+            print(json.dumps({"gather_row": row}), file=sys.stderr, flush=True)
+            del SA
+            torch.cuda.empty_cache()
+    return {"workload": "sketch of A %d x %d FP32 N(0,1) (Table 1 shape), d/n in {8, 16, 24}; kernel calls "
+                        "with the last-level cache evicted" % (m, n), "rows": rows}
 
 
 def batch_leg(reps=10):
@@ -689,6 +739,9 @@ def main():
         return
     if args.leg == "batch":
         print(json.dumps({"batch": batch_leg()}), flush=True)
+        return
+    if args.leg == "gather":
+        print(json.dumps({"gather": gather_leg()}), flush=True)
         return
     if args.leg == "ls":
         print(json.dumps({"ls": ls_leg(args.ls_solves or 5, torch.cuda.current_stream())[0]}), flush=True)
