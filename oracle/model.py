@@ -142,9 +142,12 @@ def work_item_partial(X, bk, sg, W, waves, dual, nt=TILE_COLS):
        rounded to q = rne(x * 2**S_c), S_c = 19 - h - E_c (E_c clamped to
        [-108 - h, 145 - h]); the FP32 mode adds the residual's
        z = rne((x * 2**S_c - q) * 2**21) at 2**(S_c + 21).
-    3. If more than LIST_CAP outlier records (elements x BG) arise, E_c
-       becomes binade(max |x| of the column); if a bucket row takes
-       K >= 2**(10 + h) contributions, h grows; the item is then recomputed.
+    3. The count headroom starts at h0 = the smallest h with
+       3a/2 + 64 < 2**(10 + h), a = ceil(R / W) (at most 16): a bucket row's
+       average count with room to spare.  If more than LIST_CAP outlier records
+       (elements x BG) arise, E_c becomes binade(max |x| of the column); if a
+       bucket row takes K >= 2**(10 + h) contributions, h grows; the item is
+       then recomputed.
     4. P = fl32(exact signed sum * 2**-S_c), then each outlier sign * x is
        added in FP32 (rows in order).
     """
@@ -164,6 +167,8 @@ def work_item_partial(X, bk, sg, W, waves, dual, nt=TILE_COLS):
     E = binade(M) + HEADROOM
     kall = max(int(np.bincount(bk[:, j], minlength=W).max()) if R else 0 for j in range(bg))
     h = 0
+    while h < 16 and 3 * (-(-R // W)) // 2 + 64 >= (1 << (10 + h)):
+        h += 1
     redone = False
     for attempt in range(2):
         Ec = np.clip(E, -108 - h, 145 - h)

@@ -214,8 +214,9 @@ constexpr int kBatchThreads = 1024;
 // counter (64 bits) holds the number K of contributions (low 32 bits) and of
 // negative ones N (high 32 bits), so the field sum F decodes exactly to
 // sum(sigma*q) = F - K*B + N as long as no field exceeds 2^32 (K < 2^(10+h);
-// the count headroom h is 0 unless a bucket row takes 1024 or more
-// contributions in one unit; beyond h = 16 the unit takes the float path).
+// the count headroom h starts at initial_headroom(rows of the unit, W) and
+// grows if a bucket row takes 2^(10+h) or more contributions in the unit;
+// beyond h = 16 the unit takes the float path).
 //
 // E_c comes from a sample, the first 64-row tile of every wave: each lane's
 // largest |x| in the column over its 16 rows of that tile, and
@@ -233,6 +234,20 @@ constexpr int kListCap = 1024;                 // outlier records per work item
 constexpr int kSampleRank = 4;                 // rank of the lane maximum that sets E_c
 constexpr int kHeadroom = 2;                   // binades of E_c above that lane maximum
 constexpr int kMaxHeadroom = 16;               // largest count headroom h (K < 2^26)
+
+// Count headroom a unit starts with: with a = ceil(rows / W), the average
+// count of a bucket row, the smallest h with 3a/2 + 64 < 2^(10 + h), at most
+// kMaxHeadroom.  Starting from h = 0 would recompute every unit whose
+// average alone reaches 1024 (8 bucket rows per block with 16384-row units:
+// each unit streamed twice).  The bound leaves the usual shapes at h = 0
+// (256 bucket rows, 32768-row units: 256 < 1024).
+__host__ __device__ constexpr int initial_headroom(int64_t rows, uint32_t W)
+{
+    const int64_t a = (rows + (int64_t)W - 1) / (int64_t)W;
+    int h = 0;
+    while (h < kMaxHeadroom && 3 * a / 2 + 64 >= ((int64_t)1 << (10 + h))) ++h;
+    return h;
+}
 constexpr int kCtlWords = 8 + 2 * kNT;         // control words, per-column S, per-column maximum
 constexpr int kAuxWords = 2 * kListCap;        // the outlier list; before the pass, the sample
 static_assert(kAuxWords >= 16 * 4 * kNT, "the sample of 16 waves must fit the list area");
@@ -734,7 +749,7 @@ __device__ __forceinline__ void apply_item(const ApplyArgs& p, int unit, int ct,
         }
         __syncthreads();
         int Elo = colS[2 * q], Ehi = colS[2 * q + 1];
-        int h = 0;
+        int h = initial_headroom(span, W);
         for (int attempt = 0; attempt < 2 && !fixed_ok; ++attempt) {
             if (attempt > 0) {
                 zero_lds(true);

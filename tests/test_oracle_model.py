@@ -193,3 +193,18 @@ def test_whole_call_model_gaussian_is_the_fp32_rounding_of_fp64():
     f64 = apply_f64(A, d, s, 2)
     # fl32 of the unscaled sum, then fl32 of c_s times it: within 2^-23 relative
     assert np.allclose(got, f64, rtol=2 ** -22, atol=0)
+
+
+def test_count_headroom_starts_from_the_average_bucket_count():
+    # 16384 rows over 8 bucket rows: 2048 on average, so the item starts at
+    # h = 2 (3 * 2048 / 2 + 64 < 2^12) and is not recomputed; 4096 rows over
+    # 16 bucket rows (256: 448 < 2^10) start at h = 0, 2048 over 4 (512: 832)
+    # too; the exact integer sums come out whatever h is
+    g = workloads.rng(9)
+    for R, W, h_want in ((16384, 8, 2), (4096, 16, 0), (2048, 4, 0), (6000, 4, 2)):
+        X = g.integers(-3, 4, size=(R, 2)).astype(np.float64)
+        bk = g.integers(0, W, size=(R, 1))
+        sg = np.where(g.random((R, 1)) < 0.5, -1, 1)
+        P, h, n_out, redone = model.work_item_partial(X, bk, sg, W, 8, False)
+        assert h == h_want and not redone, (R, W, h)
+        assert np.array_equal(P, _exact(X, bk, sg, W).astype(np.float32))
