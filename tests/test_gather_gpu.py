@@ -181,3 +181,31 @@ def test_gather_noalloc_falls_back_or_refuses_beyond_the_scratch():
     sk.set_schedule(gather=1)
     with pytest.raises(SketchError, match="scratch"):
         sk.apply(A, SA=SA, noalloc=True)
+
+
+def test_full_size_gather_at_the_table1_shape_on_sampled_rows():
+    # The paper's Table 1 shape (2^21 x 1024 FP32, d/n = 16, SparseStack s = 4),
+    # the launch the gather leg of bench.py times: 48 sampled rows of SA, each
+    # the oracle's FP64 sum over the rows its hash sends there (found with the
+    # C oracle's hash), rounded to FP32 once and scaled by fl32(1/2).
+    from oracle import native
+    m, n, d, s, seed = 1 << 21, 1024, 16384, 4, 3
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    A = torch.randn((m, n), generator=gen, device="cuda", dtype=torch.float32)
+    sk = Sketch(m, d, s, seed, ACC_F32)
+    assert sk.plan(0, m, n)["gather"] == 1
+    SA = sk.apply(A)
+    torch.cuda.synchronize()
+    b, g = native.hash_rows(seed, 0, m, d, s)
+    picks = np.random.default_rng(8).choice(d, size=48, replace=False)
+    got = SA[torch.from_numpy(picks).cuda()].cpu().numpy()
+    for k, bucket in enumerate(picks):
+        rows, blk = np.nonzero(b == bucket)
+        X = A[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        exact = (g[rows, blk].astype(np.float64)[:, None] * X).sum(axis=0)
+        want = (np.float32(0.5) * exact.astype(np.float32)).astype(np.float32)
+        diff = ulp_diff32(got[k].copy(), want)
+        assert diff.max() <= 1, (bucket, diff.max())
+    del A, SA
+    torch.cuda.empty_cache()
