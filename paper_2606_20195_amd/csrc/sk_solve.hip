@@ -35,11 +35,16 @@ namespace {
 
 constexpr int kT = 1024;           // threads of the row passes and one-workgroup kernels
 constexpr int kWaves = kT / 64;
-constexpr int kUT = 256;           // threads of the QR trailing update
 constexpr int kTI = 256;           // threads of the triangular inverse (one column per wave)
-constexpr int kCB = 8;             // columns per trailing-update workgroup (maximum)
+constexpr int kQB = 32;            // columns per tile of the tiled trailing update
+constexpr int kQNRB = 16;          // row blocks of its partial W = V^T C (at least 64 rows each)
+constexpr int kQR2 = 64;           // rows per workgroup of its C -= V (T^T W)
 constexpr int kMaxN = 1024;
 constexpr int64_t kQRRows = 16384;   // rows of one QR factorisation (LDS panel kernel)
+// QR scratch: T (kQB x kQB) and the partials of the tiled update (kQNRB row
+// blocks x kQB reflectors x padded columns of at most kMaxN + 1)
+constexpr int64_t kQRScratchFloats =
+    (int64_t)kQB * kQB + (int64_t)kQNRB * kQB * (((int64_t)kMaxN + 1 + kQB - 1) / kQB * kQB);
 constexpr int64_t kMaxD = 131072;    // sketch rows of sketch_solve (taller sketches: two-level QR)
 
 // Device-resident state of the refinement and of the running LSQR.
@@ -1106,156 +1111,111 @@ __global__ __launch_bounds__(kPT) void qr_panel_reg_kernel(float* M, int64_t ldm
     if (Tout && wave == 0 && lane < nb) form_t(lane, nb, gv, s_tau, Tout);
 }
 
-// Apply the panel's reflectors H_{k0} .. H_{k0+nb-1} to columns
-// [c0, c0 + ncols) of M; each workgroup owns cb columns held in LDS, and (vlds)
-// the panel's reflectors are staged in LDS once, column-major, with the
-// implicit unit diagonal and zeros above it written out.
-__global__ __launch_bounds__(kUT) void qr_update_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
-                                                         int32_t nb, int32_t c0, int32_t ncols, int32_t cb,
-                                                         const float* tau, int32_t vlds, const float* Tg)
+// Tiled trailing update, first half: for column tile x (kQB columns of the
+// trailing block, from c0) and row block y (rpb rows of the panel), the
+// partial Wp[y][i][x kQB + c] = sum over the block's rows r of V[r][i] C[r][c],
+// V the panel's reflectors (unit diagonal, zero above it), C the trailing
+// columns; padded columns and reflectors past nb hold zeros.  Rows pass
+// through LDS 64 at a time (32 lanes per row, coalesced), the next 64 in
+// registers meanwhile; thread (i, c4) owns W entries (i, 4 c4 .. 4 c4 + 3).
+__global__ __launch_bounds__(256) void qr_upd_w_kernel(const float* M, int64_t ldm, int32_t rows_total, int32_t k0,
+                                                       int32_t nb, int32_t c0, int32_t ncols, float* Wp, int64_t ncp,
+                                                       int32_t rpb)
 {
-    extern __shared__ float sm[];
-    __shared__ float red[2][kUT / 64][kCB];
+    __shared__ float Vs[64][kQB + 1];
+    __shared__ float Cs[64][kQB + 1];
     const int rows = rows_total - k0;
-    const int ldb = cb + 1;              // odd row stride: lanes of consecutive rows hit distinct banks
-    const int ldv = rows | 1;            // odd column stride of V: reflectors' rows hit distinct banks
-    float* blk = sm;                     // [rows][ldb]
-    float* V = sm + (size_t)rows * ldb;  // [nb][ldv]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cbase = c0 + blockIdx.x * cb;
-    const int nc = min(cb, c0 + ncols - cbase);
-    // staged eight loads at a time per thread
-    for (int base = 0; base < rows * cb; base += 8 * kUT) {
-        float v[8];
+    const int tid = threadIdx.x;
+    const int cb0 = blockIdx.x * kQB;
+    const int r_begin = blockIdx.y * rpb;
+    const int r_end = min(r_begin + rpb, rows);
+    const int oi = tid >> 3, oc = (tid & 7) * 4;
+    const int lj = tid & 31, lr = tid >> 5;          // staging: column lj of rows lr, lr + 8, ...
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float pv[8], pc[8];
+    auto fetch = [&](int rb) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = base + e * kUT + tid;
-            const int r = idx / cb, c = idx - r * cb;
-            v[e] = (idx < rows * cb && c < nc) ? M[(int64_t)(k0 + r) * ldm + cbase + c] : 0.0f;
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = base + e * kUT + tid;
-            const int r = idx / cb, c = idx - r * cb;
-            if (idx < rows * cb) blk[r * ldb + c] = v[e];
-        }
-    }
-    if (vlds) {
-        for (int base = 0; base < rows * nb; base += 8 * kUT) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int idx = base + e * kUT + tid;
-                const int r = idx / nb, j = idx - r * nb;
-                v[e] = (idx < rows * nb && r > j) ? M[(int64_t)(k0 + r) * ldm + k0 + j] : (r == j ? 1.0f : 0.0f);
+        for (int u = 0; u < 8; ++u) {
+            const int r = rb + lr + 8 * u;
+            float v = 0.0f, c = 0.0f;
+            if (r < r_end) {
+                const float* row = M + (int64_t)(k0 + r) * ldm;
+                if (lj < nb) v = r > lj ? row[k0 + lj] : (r == lj ? 1.0f : 0.0f);
+                if (cb0 + lj < ncols) c = row[c0 + cb0 + lj];
             }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int idx = base + e * kUT + tid;
-                const int r = idx / nb, j = idx - r * nb;
-                if (idx < rows * nb) V[(size_t)j * ldv + r] = v[e];
-            }
+            pv[u] = v;
+            pc[u] = c;
         }
-    }
-    __syncthreads();
-    if (vlds && Tg) {
-        // Block reflector: Q^T C = C - V T^T (V^T C) in three parallel phases.
-        __shared__ float Ts[32 * 32];
-        __shared__ float Wb[32][kCB + 1];
-        __shared__ float W2[32][kCB + 1];
-        for (int idx = tid; idx < nb * nb; idx += kUT) Ts[idx] = Tg[idx];
-        {   // W = V^T C: lane group of 8 per reflector i, lanes interleave the rows
-            const int i = tid >> 3, sl = tid & 7;
-            float acc[kCB];
-#pragma unroll
-            for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
-            if (i < nb) {
-                for (int r = i + sl; r < rows; r += 8) {
-                    const float v = V[(size_t)i * ldv + r];
-#pragma unroll
-                    for (int c = 0; c < kCB; ++c)
-                        if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * ldb + c], acc[c]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kCB; ++c) acc[c] = group_sum<8>(acc[c]);
-            if (sl == 0 && i < nb) {
-#pragma unroll
-                for (int c = 0; c < kCB; ++c) Wb[i][c] = acc[c];
-            }
-        }
-        __syncthreads();
-        for (int o = tid; o < nb * cb; o += kUT) {       // W2 = T^T W (T upper triangular)
-            const int i = o / cb, c = o - i * cb;
-            float acc = 0.0f;
-            for (int l = 0; l <= i; ++l) acc = __builtin_fmaf(Ts[l * nb + i], Wb[l][c], acc);
-            W2[i][c] = acc;
-        }
-        __syncthreads();
-        for (int r = tid; r < rows; r += kUT) {          // C -= V W2 (V is zero above its diagonal)
-            float acc[kCB];
-#pragma unroll
-            for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
-            const int imax = min(nb - 1, r);
-            for (int i = 0; i <= imax; ++i) {
-                const float v = V[(size_t)i * ldv + r];
-#pragma unroll
-                for (int c = 0; c < kCB; ++c) acc[c] = __builtin_fmaf(v, W2[i][c], acc[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < kCB; ++c)
-                if (c < cb) blk[r * ldb + c] -= acc[c];
-        }
-        __syncthreads();
-        for (int idx = tid; idx < rows * cb; idx += kUT) {
-            const int r = idx / cb, c = idx - r * cb;
-            if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[r * ldb + c];
-        }
-        return;
-    }
-    auto vval = [&](int j, int r) -> float {
-        if (vlds) return V[(size_t)j * ldv + r];
-        return r < j ? 0.0f : (r == j ? 1.0f : M[(int64_t)(k0 + r) * ldm + k0 + j]);
     };
-    for (int j = 0; j < nb; ++j) {
-        const float t = tau[k0 + j];
-        if (t == 0.0f) continue;
-        float acc[kCB];
+    if (r_begin < r_end) fetch(r_begin);
+    for (int rb = r_begin; rb < r_end; rb += 64) {
 #pragma unroll
-        for (int c = 0; c < kCB; ++c) acc[c] = 0.0f;
-        for (int r = j + tid - (j % kUT); r < rows; r += kUT) {
-            if (r < j) continue;
-            const float v = vval(j, r);
-#pragma unroll
-            for (int c = 0; c < kCB; ++c)
-                if (c < cb) acc[c] = __builtin_fmaf(v, blk[r * ldb + c], acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < kCB; ++c) {
-            acc[c] = group_sum<64>(acc[c]);
-            if (lane == 0) red[j & 1][wave][c] = acc[c];
+        for (int u = 0; u < 8; ++u) {
+            Vs[lr + 8 * u][lj] = pv[u];
+            Cs[lr + 8 * u][lj] = pc[u];
         }
         __syncthreads();
-        float w[kCB];
+        if (rb + 64 < r_end) fetch(rb + 64);
+#pragma unroll 8
+        for (int rr = 0; rr < 64; ++rr) {
+            const float v = Vs[rr][oi];
 #pragma unroll
-        for (int c = 0; c < kCB; ++c) {
-            float sum = 0.0f;
-#pragma unroll
-            for (int q = 0; q < kUT / 64; ++q) sum += red[j & 1][q][c];
-            w[c] = sum * t;
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(v, Cs[rr][oc + q], acc[q]);
         }
-        for (int r = j + tid - (j % kUT); r < rows; r += kUT) {
-            if (r < j) continue;
-            const float v = vval(j, r);
+        __syncthreads();
+    }
+    float* dst = Wp + ((int64_t)blockIdx.y * kQB + oi) * ncp + cb0 + oc;
 #pragma unroll
-            for (int c = 0; c < kCB; ++c)
-                if (c < cb) blk[r * ldb + c] = __builtin_fmaf(-w[c], v, blk[r * ldb + c]);
-        }
+    for (int q = 0; q < 4; ++q) dst[q] = acc[q];
+}
+
+// Second half: W = the nrb partials of the tile summed in row-block order,
+// W2 = T^T W (T upper triangular, nb x nb row-major), then rows of the block
+// eight at a time: lane c of row slot rr subtracts sum_i V[r][i] W2[i][c]
+// from column c (the row's V staged in LDS, the tile's columns coalesced).
+__global__ __launch_bounds__(256) void qr_upd_c_kernel(float* M, int64_t ldm, int32_t rows_total, int32_t k0,
+                                                       int32_t nb, int32_t c0, int32_t ncols, const float* Wp,
+                                                       int32_t nrb, int64_t ncp, const float* Tg)
+{
+    __shared__ float W[kQB][kQB + 1];
+    __shared__ float W2[kQB][kQB + 1];
+    __shared__ float Ts[kQB][kQB + 1];
+    __shared__ float Vs[2][8][kQB + 1];
+    const int rows = rows_total - k0;
+    const int tid = threadIdx.x;
+    const int cb0 = blockIdx.x * kQB;
+    for (int e = tid; e < kQB * kQB; e += 256) {
+        const int i = e >> 5, c = e & 31;
+        float sum = 0.0f;
+        for (int y = 0; y < nrb; ++y) sum += Wp[((int64_t)y * kQB + i) * ncp + cb0 + c];
+        W[i][c] = sum;
+        Ts[i][c] = (i < nb && c < nb) ? Tg[i * nb + c] : 0.0f;
     }
     __syncthreads();
-    for (int idx = tid; idx < rows * cb; idx += kUT) {
-        const int r = idx / cb, c = idx - r * cb;
-        if (c < nc) M[(int64_t)(k0 + r) * ldm + cbase + c] = blk[r * ldb + c];
+    for (int e = tid; e < kQB * kQB; e += 256) {
+        const int i = e >> 5, c = e & 31;
+        float a = 0.0f;
+        for (int l = 0; l <= i; ++l) a = __builtin_fmaf(Ts[l][i], W[l][c], a);
+        W2[i][c] = a;
+    }
+    const int c = tid & 31, rr = tid >> 5;
+    const bool live = cb0 + c < ncols;
+    const int r_begin = blockIdx.y * kQR2, r_end = min(r_begin + kQR2, rows);
+    int buf = 0;
+    for (int rb = r_begin; rb < r_end; rb += 8, buf ^= 1) {
+        const int r = rb + rr;
+        float* row = M + (int64_t)(k0 + r) * ldm;
+        float v = 0.0f, cv = 0.0f;
+        if (r < r_end) {
+            if (c < nb) v = r > c ? row[k0 + c] : (r == c ? 1.0f : 0.0f);
+            if (live) cv = row[c0 + cb0 + c];
+        }
+        Vs[buf][rr][c] = v;
+        __syncthreads();        // also orders W2 before its first use
+        float a = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kQB; ++i) a = __builtin_fmaf(Vs[buf][rr][i], W2[i][c], a);
+        if (r < r_end && live) row[c0 + cb0 + c] = cv - a;
     }
 }
 
@@ -1410,13 +1370,6 @@ int panel_width(int64_t rows)
     return 0;
 }
 
-int update_cols(int64_t rows)
-{
-    for (int cb : {kCB, 4, 2, 1})
-        if (rows * (cb + 1) * 4 <= 150 * 1024) return cb;
-    return 0;
-}
-
 hipError_t set_lds(const void* fn, size_t bytes)
 {
     if (bytes <= 64 * 1024) return hipSuccess;
@@ -1453,21 +1406,23 @@ hipError_t run_qr(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ncols > 0) {
-            // reflectors in LDS when they fit beside at least 4 columns, else read from L2
-            int cb = 0, vlds = 0;
-            for (int c : {kCB, 4}) {
-                if (((size_t)prow * (c + 1) + (size_t)nb * (prow | 1)) * 4 <= 150 * 1024) {
-                    cb = c;
-                    vlds = 1;
-                    break;
-                }
-            }
-            if (!cb) cb = update_cols(prow);
-            const size_t ulds = ((size_t)prow * (cb + 1) + (vlds ? (size_t)nb * (prow | 1) : 0)) * 4;
-            if ((e = set_lds((const void*)qr_update_kernel, ulds)) != hipSuccess) return e;
-            hipLaunchKernelGGL(qr_update_kernel, dim3((unsigned)((ncols + cb - 1) / cb)), dim3(kUT), ulds, st, M,
-                               ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0, (int32_t)ncols,
-                               (int32_t)cb, (const float*)tau, (int32_t)vlds, (const float*)T);
+            // C -= V T^T (V^T C) in two tiled kernels: partial V^T C per
+            // (column tile, row block) into the scratch after T, then the sum
+            // of the partials in row-block order and the rank-nb update
+            // up to kQNRB row blocks of a multiple of 64 rows: enough workgroups
+            // for short panels, a few staged chunks each for tall ones
+            const int64_t ncb = (ncols + kQB - 1) / kQB, ncp = ncb * kQB;
+            const int64_t rpb = ((prow + kQNRB - 1) / kQNRB + 63) / 64 * 64;
+            const int64_t nrb = (prow + rpb - 1) / rpb;
+            if (nrb > kQNRB || nrb * kQB * ncp > kQRScratchFloats - kQB * kQB) return hipErrorInvalidValue;
+            float* Wp = T + kQB * kQB;
+            hipLaunchKernelGGL(qr_upd_w_kernel, dim3((unsigned)ncb, (unsigned)nrb), dim3(256), 0, st,
+                               (const float*)M, ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0,
+                               (int32_t)ncols, Wp, ncp, (int32_t)rpb);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(qr_upd_c_kernel, dim3((unsigned)ncb, (unsigned)((prow + kQR2 - 1) / kQR2)), dim3(256),
+                               0, st, M, ldm, (int32_t)rows, (int32_t)k0, (int32_t)nb, (int32_t)c0, (int32_t)ncols,
+                               (const float*)Wp, (int32_t)nrb, ncp, (const float*)T);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         k0 += nb;
@@ -1604,7 +1559,7 @@ struct SolveJob {
     uint16_t* SA16 = nullptr;
     float* b32 = nullptr;
     float* tau = nullptr;
-    float* Tq = nullptr;         // 32 x 32 block-reflector factor of the current QR panel
+    float* Tq = nullptr;         // QR scratch: the panel's 32 x 32 block-reflector factor, then update partials
     // host resources (kept across reuses)
     SolveState* host = nullptr;  // pinned
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1702,7 +1657,7 @@ int job_prepare(SolveJob* j, const sk_sketch& S, const void* A, int32_t a_dtype,
     j->oP = take((size_t)n * n * 4);
     j->oPT = take((size_t)n * n * 4);
     j->otau = take((size_t)n * 4 + 4);
-    j->oTq = take(32 * 32 * 4);
+    j->oTq = take((size_t)kQRScratchFloats * 4);
     // Sketches taller than one QR: factor row blocks of at most kQRRows rows,
     // stack their triangles (with the transformed Sb) and factor the stack.
     j->qr_blocks = (int32_t)((d + kQRRows - 1) / kQRRows);
@@ -2026,10 +1981,11 @@ int sketch_qr_f32(float* M, int64_t rows, int64_t cols, int64_t ldm, int64_t k, 
     if (rows > kQRRows || cols > kMaxN + 1)
         return set_error(SK_EUNSUPPORTED, "rows <= %lld and cols <= %d", (long long)kQRRows, kMaxN + 1);
     if (k == 0) return SK_OK;
-    // the block reflectors' 32 x 32 factor, allocated in stream order
+    // the block reflectors' 32 x 32 factor and the update's partials,
+    // allocated in stream order
     hipStream_t st = (hipStream_t)stream;
     float* T = nullptr;
-    hipError_t e = hipMallocAsync((void**)&T, 32 * 32 * 4, st);
+    hipError_t e = hipMallocAsync((void**)&T, (size_t)kQRScratchFloats * 4, st);
     if (e != hipSuccess) return set_error(SK_ENOMEM, "QR factor buffer: %s", hipGetErrorString(e));
     e = run_qr(M, rows, cols, ldm, k, tau, T, st);
     const hipError_t ef = hipFreeAsync(T, st);
