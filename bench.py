@@ -405,13 +405,22 @@ def batch_leg(reps=10):
             sk.apply(sp["A"], SA=sp["SA"])
     sep_ms = timed(separate)
     gbs = lambda t: round(total / (t * 1e-3) / 1e9, 1)   # noqa: E731
+    # the same problems by width, one persistent launch per subset (planned schedule)
+    clear_tuning()
+    by_width = {}
+    for n in sorted({sp["A"].shape[1] for sp in specs}):
+        sub = [sp for sp in specs if sp["A"].shape[1] == n]
+        byt = sum(sp["A"].shape[0] * n * 2 + sp["d"] * n * 2 for sp in sub)
+        t = timed(Batch(sub).apply)
+        by_width["n=%d" % n] = {"problems": len(sub), "GB": round(byt / 1e9, 3), "ms": round(t, 4),
+                                "GB/s": round(byt / (t * 1e-3) / 1e9, 1)}
     return {"workload": "512 sketches, m = floor(2^(12+8U)), n in {8,16,32,64,128}, d = 4n, s = 4, FP16-RN, "
                         "10% coherent", "algorithmic_bytes": total,
             "persistent_ms": round(ms, 4), "persistent_GB/s": gbs(ms),
             "persistent_pct_of_peak": round(100 * total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1),
             "graph_ms": round(gms, 4), "graph_GB/s": gbs(gms),
             "separate_ms": round(sep_ms, 4), "separate_GB/s": gbs(sep_ms),
-            "untuned_persistent_ms": round(default_ms, 4), "tuned_schedule": tuned}
+            "untuned_persistent_ms": round(default_ms, 4), "tuned_schedule": tuned, "by_width": by_width}
 
 
 def serve_leg(count, warm):

@@ -79,18 +79,26 @@ __global__ __launch_bounds__(kScanThreads) void gather_scan_kernel(uint32_t* cnt
     if (threadIdx.x == kScanThreads - 1) off[d] = part[kScanThreads - 1];
 }
 
+// The four blocks of one hash call take their list slots with four atomics
+// in flight before the entries are stored.
 __global__ __launch_bounds__(kGatherThreads) void gather_fill_kernel(ApplyArgs p, uint32_t* cur, uint32_t* list)
 {
     const int64_t stride = (int64_t)gridDim.x * kGatherThreads;
     for (int64_t r = (int64_t)blockIdx.x * kGatherThreads + threadIdx.x; r < p.rows; r += stride) {
         const uint64_t gr = (uint64_t)(p.row_offset + r);
-        uint4 w4 = make_uint4(0u, 0u, 0u, 0u);
-        for (int j = 0; j < p.s; ++j) {
-            if ((j & 3) == 0) w4 = row_words(gr, (uint32_t)j >> 2, p.k0, p.k1);
-            const uint32_t w = word_of(w4, (uint32_t)j & 3u);
-            const uint32_t b = (uint32_t)j * p.W + bucket_in_block(w, p.W);
-            const uint32_t at = __hip_atomic_fetch_add(&cur[b], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            list[at] = (uint32_t)r | ((w & 1u) << 31);
+        for (int j0 = 0; j0 < p.s; j0 += 4) {
+            const uint4 w4 = row_words(gr, (uint32_t)j0 >> 2, p.k0, p.k1);
+            const uint32_t w[4] = {w4.x, w4.y, w4.z, w4.w};
+            uint32_t at[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + u < p.s) {
+                    const uint32_t b = (uint32_t)(j0 + u) * p.W + bucket_in_block(w[u], p.W);
+                    at[u] = __hip_atomic_fetch_add(&cur[b], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j0 + u < p.s) list[at[u]] = (uint32_t)r | ((w[u] & 1u) << 31);
         }
     }
 }
