@@ -46,7 +46,8 @@ def _row_sign_normalise(R):
 @pytest.mark.parametrize("rows,n,zero_col", [
     (256, 32, None), (1024, 256, None), (300, 37, None), (2048, 40, None), (65, 64, None), (96, 1, None),
     (1200, 40, None), (1200, 300, None), (500, 50, None), (4096, 100, None),   # panels of 17-31 columns
-    (768, 200, None), (640, 70, 5)])                                            # a zero column
+    (768, 200, None), (640, 70, 5),                                             # a zero column
+    (16384, 48, None), (2100, 1024, None)])   # 16 row blocks of 1024 rows; 33 column tiles of the update
 def test_qr_matches_fp64(rows, n, zero_col):
     M = workloads.gaussian(rows, n + 1, 11 + n, np.float32)
     if zero_col is not None:
