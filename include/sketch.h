@@ -157,11 +157,15 @@ int sketch_destroy(sk_handle h);
  * BF16 round-to-nearest addition under SK_ACCUMULATE.  BF16 SA needs 2-byte
  * alignment only.  BF16 handles are not accepted by batches, sketch_solve or
  * the request server (SK_EUNSUPPORTED).
- * When d/s bucket rows of 32 FP32 values do not fit in LDS (d/s above about
- * 1200), the whole call is one unit: its unscaled contributions are summed
- * with FP32 atomics in a d x n FP32 workspace that the handle allocates on
- * first need and keeps, then scaled and (FP16 modes) rounded once per entry
- * at sites q = row_offset*d*n + b*n + c.  That path is much slower.
+ * Large d/s: the partials take narrower column tiles (8, 4 or 2 columns)
+ * as d/s grows.  When only a tile narrower than the width calls for fits (or
+ * none), the whole call is one unit summed into a d x n FP32 workspace that
+ * the handle allocates on first need and keeps (with, for the gather, its
+ * bucket lists: 3d + rows*s 32-bit words): by the bucket-sorted gather (rows
+ * of 256 bytes or more; 64 or more when no tile fits), whose entries are
+ * the FP32 rounding of their FP64 sums, or else by FP32 atomics per
+ * contribution; the sum is then scaled and (16-bit modes) rounded once per
+ * entry at sites q = row_offset*d*n + b*n + c.  sketch_plan reports which.
  * The call enqueues work on `stream` and returns; it does not synchronise.
  * Errors: SK_EINVAL (shapes, pointers, flags), SK_EUNSUPPORTED (alignment, a
  * forced block_group that does not fit), SK_ENOMEM, SK_EHIP.
@@ -179,8 +183,12 @@ int sketch_apply(sk_handle h, const void *A, int32_t a_dtype, int64_t rows, int6
  * output, FP32 accumulation into SA with a non-power-of-two 1/sqrt(s)), it
  * uses instead a static device scratch array of 4194304 floats (16 MiB) that
  * the library holds on each GPU it runs on until the process ends; it clears
- * what it uses with a fill kernel.  Calls that would need more than
- * d * n = 4194304 workspace floats fail with SK_EINVAL.  Every call on one
+ * what it uses with a fill kernel (the gather's counters; its other arrays
+ * are written whole before they are read).  Calls that would need more than
+ * 4194304 workspace floats fail with SK_EINVAL; where the planner chose the
+ * bucket-sorted gather and its lists do not fit beside the d x n sum, the
+ * call takes the FP32-atomic workspace path instead (a schedule that forces
+ * the gather fails).  Every call on one
  * GPU shares that GPU's scratch: calls that overlap on one GPU (two streams,
  * two threads) race and give wrong results.
  */
