@@ -209,3 +209,29 @@ def test_full_size_gather_at_the_table1_shape_on_sampled_rows():
         assert diff.max() <= 1, (bucket, diff.max())
     del A, SA
     torch.cuda.empty_cache()
+
+
+def test_tuner_weighs_the_gather_and_records_the_path(tmp_path):
+    # A large-d/s sketch of wide rows: the single-apply tuner times the LDS
+    # tiles, the FP32 atomics and the bucket-sorted gather, keeps the fastest
+    # (the gather here), writes every schedule field of it to the JSON file,
+    # and the planner then follows the table; the result stays exact.
+    import json
+    from paper_2606_20195_amd import clear_tuning, load_tuning
+    clear_tuning()
+    m, n, d, s = 200000, 256, 16384, 4
+    A = workloads.integers(m, n, seed=60, lim=4)
+    Ad = to_dev(A)
+    sk = Sketch(m, d, s, 22, ACC_F32)
+    path = str(tmp_path / "tune.json")
+    tuned = sk.tune(Ad, cache_path=path)
+    assert tuned["gather"] == 1 and tuned["global_atomics"] == 0
+    entry = json.load(open(path))["entries"][-1]
+    assert entry["gather"] == 1 and "col_tile" in entry and "global_atomics" in entry
+    clear_tuning()
+    assert load_tuning(path) >= 1
+    assert sk.plan(0, m, n)["gather"] == 1
+    got = sk.apply(Ad)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), model.apply_f32_exact_int(A, d, s, 22))
+    clear_tuning()
