@@ -958,52 +958,79 @@ __global__ __launch_bounds__(kT) void qr_panel_kernel(float* M, int64_t ldm, int
             __syncthreads();
         }
     } else {
+        // One sweep per step: the pivot's norm comes from the previous step's
+        // update of that column (its group sums the squares as it writes
+        // them), the other columns use the unscaled pivot with the scale
+        // folded into their coefficients, and the pivot column is scaled one
+        // step later, when no group reads it.
         const int G = nb > 16 ? 32 : 64;     // lanes per column group: kT / G >= nb groups
         const int grp = tid / G, gl = tid % G;
+        __shared__ float sig_s[32];
+        __shared__ float scal_s[32];
+        if (grp == 0) {
+            const float* x = pan;
+            float s4 = 0.0f;
+            for (int r = 1 + gl; r < rows; r += G) s4 = __builtin_fmaf(x[r], x[r], s4);
+            s4 = sum_lanes(s4, G);
+            if (gl == 0) sig_s[0] = s4;
+        }
+        __syncthreads();
         for (int j = 0; j < nb; ++j) {
-            if (grp == j) {
+            if (tid == 0) {
                 float* x = pan + j * ldl;
-                float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                int r = j + 1 + gl;
-                for (; r + 3 * G < rows; r += 4 * G) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) s4[e] = __builtin_fmaf(x[r + e * G], x[r + e * G], s4[e]);
-                }
-                for (; r < rows; r += G) s4[0] = __builtin_fmaf(x[r], x[r], s4[0]);
-                float sig = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-                sig = sum_lanes(sig, G);
-                const float x0 = x[j];
-                float t = 0.0f, beta = x0;
+                const float x0 = x[j], sig = sig_s[j];
+                float t = 0.0f, beta = x0, scal = 0.0f;
                 if (sig > 0.0f) {
                     beta = -copysignf(sqrtf(__builtin_fmaf(x0, x0, sig)), x0);
                     t = (beta - x0) / beta;
-                    const float scal = 1.0f / (x0 - beta);
-                    for (int r = j + 1 + gl; r < rows; r += G) x[r] *= scal;
+                    scal = 1.0f / (x0 - beta);
                 }
-                if (gl == 0) {
-                    x[j] = beta;
-                    s_tau[j] = t;
-                }
+                x[j] = beta;
+                s_tau[j] = t;
+                scal_s[j] = scal;
             }
             __syncthreads();
+            if (j >= 1 && grp == j - 1) {
+                float* x = pan + (j - 1) * ldl;
+                const float scal = scal_s[j - 1];
+                for (int r = j + gl; r < rows; r += G) x[r] *= scal;
+            }
             if (grp > j && grp < nb) {
-                const float t = s_tau[j];
+                const float t = s_tau[j], scal = scal_s[j];
+                const float* x = pan + j * ldl;
+                float* yc = pan + grp * ldl;
+                float ss = 0.0f;
                 if (t != 0.0f) {
-                    const float* v = pan + j * ldl;
-                    float* yc = pan + grp * ldl;
-                    float w4[4] = {gl == 0 ? yc[j] : 0.0f, 0.0f, 0.0f, 0.0f};
+                    float w4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                     int r = j + 1 + gl;
                     for (; r + 3 * G < rows; r += 4 * G) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) w4[e] = __builtin_fmaf(v[r + e * G], yc[r + e * G], w4[e]);
+                        for (int e = 0; e < 4; ++e) w4[e] = __builtin_fmaf(x[r + e * G], yc[r + e * G], w4[e]);
                     }
-                    for (; r < rows; r += G) w4[0] = __builtin_fmaf(v[r], yc[r], w4[0]);
-                    float w = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-                    w = sum_lanes(w, G) * t;
+                    for (; r < rows; r += G) w4[0] = __builtin_fmaf(x[r], yc[r], w4[0]);
+                    const float dot = sum_lanes((w4[0] + w4[1]) + (w4[2] + w4[3]), G);
+                    const float w = __builtin_fmaf(scal, dot, yc[j]) * t;
                     if (gl == 0) yc[j] -= w;
-                    for (int r = j + 1 + gl; r < rows; r += G) yc[r] = __builtin_fmaf(-w, v[r], yc[r]);
+                    const float ws = w * scal;
+                    for (int r2 = j + 1 + gl; r2 < rows; r2 += G) {
+                        const float y = __builtin_fmaf(-ws, x[r2], yc[r2]);
+                        yc[r2] = y;
+                        if (r2 > j + 1) ss = __builtin_fmaf(y, y, ss);
+                    }
+                } else if (grp == j + 1) {
+                    for (int r2 = j + 2 + gl; r2 < rows; r2 += G) ss = __builtin_fmaf(yc[r2], yc[r2], ss);
+                }
+                if (grp == j + 1) {
+                    ss = sum_lanes(ss, G);
+                    if (gl == 0) sig_s[j + 1] = ss;
                 }
             }
+            __syncthreads();
+        }
+        if (grp == nb - 1) {
+            float* x = pan + (nb - 1) * ldl;
+            const float scal = scal_s[nb - 1];
+            for (int r = nb + gl; r < rows; r += G) x[r] *= scal;
         }
     }
     __syncthreads();
